@@ -1,0 +1,139 @@
+"""ctypes front end of the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+SPLINE = 0
+PLUMMER = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(_HERE, "oracle_nf.c")
+_LIB = os.path.join(_HERE, "liboracle_nf.so")
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def compile_oracle(src: str, out: str) -> str:
+    """gcc -O3 with OpenMP and IEEE FP64 (no fast-math, no FMA contraction)."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(SOURCE):
+        compile_oracle(SOURCE, _LIB)
+    return _LIB
+
+
+def _pos32(pos) -> np.ndarray:
+    p = np.ascontiguousarray(pos, dtype=np.float32)
+    if p.ndim != 2 or p.shape[1] != 3:
+        raise ValueError("positions must be [n, 3]")
+    return p
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+class Oracle:
+    """One loaded build of oracle_nf.c."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        c_i64, c_d, vp, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+        lib.oracle_nf_bin.argtypes = [vp, c_i64, c_d, ci, vp]
+        lib.oracle_nf_kernel.argtypes = [vp, c_i64, c_d, ci, vp]
+        lib.oracle_nf_forces.argtypes = [vp, c_i64, c_d, ci, ci, c_d, ci, c_d, vp, c_i64, ci, ci, vp, vp]
+        lib.oracle_nf_count_pairs.argtypes = [vp, c_i64, c_d, ci, ci, vp]
+        for f in (lib.oracle_nf_bin, lib.oracle_nf_kernel, lib.oracle_nf_forces, lib.oracle_nf_count_pairs):
+            f.restype = ctypes.c_int
+        self.lib = lib
+        self.path = path
+
+    def bin_cells(self, pos, box: float, K: int) -> np.ndarray:
+        """Linear cell index of every particle by the oracle's cell rule."""
+        p = _pos32(pos)
+        out = np.empty(p.shape[0], dtype=np.int32)
+        _check(self.lib.oracle_nf_bin(p.ctypes.data, p.shape[0], float(box), int(K), out.ctypes.data), "bin")
+        return out
+
+    def kernel_g(self, r, eps: float, kind: int = SPLINE) -> np.ndarray:
+        """The softened inverse cube g(r) (0 at r=0)."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        out = np.empty_like(r)
+        _check(self.lib.oracle_nf_kernel(r.ctypes.data, r.size, float(eps), int(kind), out.ctypes.data), "kernel")
+        return out
+
+    def forces(self, pos, box: float, K: int, R: int, eps: float, kind: int = SPLINE, gm: float = 1.0,
+               sinks: Optional[np.ndarray] = None, neumaier: bool = False, threads: int = 0,
+               return_pairs: bool = False):
+        """FP64 near-field accelerations [m,3] of the sinks (all particles by default)."""
+        p = _pos32(pos)
+        n = p.shape[0]
+        if sinks is None:
+            m, sp = n, None
+        else:
+            sk = np.ascontiguousarray(sinks, dtype=np.int64)
+            m, sp = sk.size, sk.ctypes.data
+        acc = np.zeros((m, 3), dtype=np.float64)
+        pairs = ctypes.c_int64(0)
+        rc = self.lib.oracle_nf_forces(p.ctypes.data if n else None, n, float(box), int(K), int(R), float(eps),
+                                       int(kind), float(gm), sp, m, int(bool(neumaier)), int(threads),
+                                       acc.ctypes.data if m else None, ctypes.byref(pairs))
+        _check(rc, "forces")
+        return (acc, int(pairs.value)) if return_pairs else acc
+
+    def count_pairs(self, pos, box: float, K: int, R: int = 2) -> int:
+        """Exact number of (sink, source) pairs, self pairs included, from cell occupancy."""
+        p = _pos32(pos)
+        out = ctypes.c_int64(0)
+        _check(self.lib.oracle_nf_count_pairs(p.ctypes.data if p.shape[0] else None, p.shape[0], float(box),
+                                              int(K), int(R), ctypes.byref(out)), "count_pairs")
+        return int(out.value)
+
+
+_default: Optional[Oracle] = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _default = Oracle(_LIB)
+    return _default
+
+
+def bin_cells(pos, box, K):
+    return default().bin_cells(pos, box, K)
+
+
+def kernel_g(r, eps, kind=SPLINE):
+    return default().kernel_g(r, eps, kind)
+
+
+def forces(pos, box, K, R, eps, kind=SPLINE, gm=1.0, sinks=None, neumaier=False, threads=0, return_pairs=False):
+    return default().forces(pos, box, K, R, eps, kind, gm, sinks, neumaier, threads, return_pairs)
+
+
+def count_pairs(pos, box, K, R=2):
+    return default().count_pairs(pos, box, K, R)
+
+
+def forces_boxes(boxes: Sequence, R: int = 2, kind: int = SPLINE, threads: int = 0) -> np.ndarray:
+    """Concatenated accelerations for a list of independent boxes (workloads.Box)."""
+    out = [forces(b.pos, b.box, b.K, R, b.eps, kind, b.gm, threads=threads) for b in boxes]
+    return np.concatenate(out, axis=0) if out else np.zeros((0, 3))
