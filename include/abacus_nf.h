@@ -1,0 +1,228 @@
+/*
+ * abacus_nf.h -- near-field direct force of the Abacus N-body method on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation (Sec. 3.1 "Force Solver Algorithm and Serial Method" of
+ * Maksimova et al., AbacusSummit): a cubic periodic box of side L is cut into
+ * K^3 cells.  The near field of a particle is every particle in the cells
+ * within R cells of its own cell (R = 2: the 5x5x5 block), each taken at the
+ * periodic image that lies in that neighbouring cell.  Its acceleration is the
+ * direct O(N^2) sum over that set,
+ *
+ *     a_i = G*m * sum_j d_ij * g(|d_ij|),   d_ij = x_j' - x_i,
+ *
+ * with g the softened inverse cube: the spline law that is exactly Newtonian
+ * beyond the softening length (Sec. 2.4 "Code Parameters", Sec. 5.2
+ * "Accuracy") or Plummer's g = (r^2 + eps^2)^(-3/2) (Sec. 5.2).  The spline
+ * interior used here is the cubic force polynomial whose value, slope and
+ * curvature match 1/r^2 at r = eps: |F| eps^2 = 10u - 15u^2 + 6u^3, u = r/eps.
+ *
+ * Cell rule: along each axis xt = x - L*floor(x/L), c = min(floor(xt*K/L), K-1),
+ * evaluated in FP64 from the FP32 input with every operation rounded on its
+ * own; linear cell index (cx*K + cy)*K + cz.  Positions outside [0, L) are
+ * wrapped.  Coincident particles (and the self pair) contribute zero.
+ *
+ * Conventions for every entry point:
+ *   - Return value: ABACUS_NF_OK (0) or a negative error code below.
+ *   - Argument errors are detected and returned synchronously, before any
+ *     work is enqueued and before any HIP call.
+ *   - Errors found on the device (non-finite input, work-list overflow) are
+ *     recorded in a per-device error word and returned by abacus_nf_sync.
+ *   - "Device pointer" means memory of the current HIP device (for example
+ *     a torch tensor's data_ptr()).  hip_stream is a hipStream_t (NULL = the
+ *     legacy default stream).  Work is enqueued on that stream in order;
+ *     build_cells and forces do not block the host.
+ *   - A handle must be used from one stream at a time; the library is not
+ *     thread-safe for concurrent calls on the same handle.
+ */
+#ifndef ABACUS_NF_H
+#define ABACUS_NF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABACUS_NF_OK 0
+#define ABACUS_NF_EINVAL -1     /* bad argument                                   */
+#define ABACUS_NF_ENOMEM -2     /* device or host allocation failed               */
+#define ABACUS_NF_EDEVICE -3    /* a HIP call failed                              */
+#define ABACUS_NF_ECAPACITY -4  /* a device-side list outgrew its allocation      */
+#define ABACUS_NF_ENONFINITE -5 /* a position was NaN or infinite                 */
+#define ABACUS_NF_ESTATE -6     /* handle used in the wrong state                 */
+
+/* Softening law (Sec. 2.4, Sec. 5.2). */
+typedef enum {
+    ABACUS_NF_SPLINE = 0,  /* exactly 1/r^2 beyond eps; cubic force polynomial inside */
+    ABACUS_NF_PLUMMER = 1  /* potential -1/sqrt(r^2 + eps^2)                          */
+} abacus_nf_kind;
+
+/* How each sink's sum of FP32 pair terms is accumulated. */
+typedef enum {
+    ABACUS_NF_SUM_FP32 = 0,   /* one plain FP32 running sum per sink                       */
+    ABACUS_NF_SUM_COMP32 = 1, /* FP32 block sums folded with two-sum into an FP32 (hi, lo)
+                                 pair; the final per-particle reduction across lanes and
+                                 source parts is FP64                                       */
+    ABACUS_NF_SUM_FP64 = 2    /* every FP32 pair term added into an FP64 sum (comparison)   */
+} abacus_nf_sum;
+
+/* One periodic box of a batch: particles pos[offset .. offset+n) of the
+ * position array, side L = box, K cells per side.  The boxes of a batch
+ * partition the position array in order: offset of box 0 is 0, each next box
+ * starts where the previous ends, and the sizes add up to n_total. */
+typedef struct {
+    int64_t offset;
+    int64_t n;
+    double box;
+    int32_t K;
+    int32_t reserved; /* must be 0 */
+} abacus_nf_box;
+
+/* Opaque, library-owned cell structure of one batch of boxes. */
+typedef struct abacus_nf_cells_s *abacus_nf_cells;
+
+/*
+ * abacus_nf_build_cells -- sort the particles into cells (Sec. 3.1: the
+ * cubic lattice of CPD^3 cells per box).
+ *
+ *   pos      device float32 [n_total][3], x y z of each particle, any order.
+ *            Read by the enqueued work only; the handle keeps its own sorted,
+ *            cell-relative copy, so pos may be reused once that work is done.
+ *   n_total  number of particles (0 <= n_total < 2^31).
+ *   boxes    host array [n_boxes], copied during the call.
+ *   n_boxes  1 <= n_boxes <= 65536.
+ *   R        near-field radius in cells (1 <= R <= 3; every box needs K >= 2R+1;
+ *            the sum over boxes of K^3 must be below 2^31).
+ *   cells    in/out.  If *cells is NULL a new handle is allocated.  If it holds
+ *            a handle from an earlier call, that handle is rebuilt in place
+ *            when its allocations are large enough (no allocation, so the call
+ *            may be captured in a HIP graph), and reallocated otherwise.
+ *
+ * Enqueues: binning, a stable sort of particles by cell (input order within a
+ * cell), the cell offsets, and the cell-relative FP32 coordinates.
+ * Errors: EINVAL for bad arguments; ENOMEM; EDEVICE.  Non-finite positions
+ * are reported later by abacus_nf_sync as ENONFINITE.
+ */
+int abacus_nf_build_cells(const float *pos, int64_t n_total, const abacus_nf_box *boxes,
+                          int32_t n_boxes, int32_t R, void *hip_stream, abacus_nf_cells *cells);
+
+/*
+ * abacus_nf_forces -- near-field accelerations of every particle (Sec. 3.1
+ * direct sum; softening of Sec. 2.4 / Sec. 5.2).
+ *
+ *   cells  a handle filled by abacus_nf_build_cells on the same stream.
+ *   eps    host double [n_boxes]: softening length of each box in the box's
+ *          length unit (the spline radius for SPLINE, the Plummer length for
+ *          PLUMMER).  Valid range: 1e-5 <= eps*K/L <= 1.
+ *   kind   ABACUS_NF_SPLINE or ABACUS_NF_PLUMMER.
+ *   gm     host double [n_boxes]: G times the particle mass of each box.
+ *   mode   accumulation mode (abacus_nf_sum).
+ *   acc    device float32 [n_total][3], written in the input order of pos.
+ *          Valid after abacus_nf_sync or for later work on the same stream.
+ *
+ * Allocates nothing when the handle already holds the work buffers of an
+ * earlier forces call of the same batch (so it may be captured in a HIP
+ * graph after one eager call).
+ * Errors: EINVAL, ESTATE (handle not built), ENOMEM, EDEVICE; ECAPACITY is
+ * reported by abacus_nf_sync if a device work list overflows.
+ */
+int abacus_nf_forces(abacus_nf_cells cells, const double *eps, abacus_nf_kind kind, const double *gm,
+                     abacus_nf_sum mode, float *acc, void *hip_stream);
+
+/*
+ * abacus_nf_sync -- wait for the stream, then return (and clear) the first
+ * error recorded on the current device since the last sync: ENONFINITE,
+ * ECAPACITY, or EDEVICE if the stream itself failed.
+ */
+int abacus_nf_sync(void *hip_stream);
+
+/* Release a handle and its device memory (waits for the device first).  NULL is accepted. */
+int abacus_nf_free_cells(abacus_nf_cells cells);
+
+/* Static description of an error code; never NULL. */
+const char *abacus_nf_strerror(int code);
+
+/*
+ * abacus_nf_interactions -- exact number of (sink, source) pairs the forces
+ * call evaluates for this handle, self pairs included: the sum over cells c
+ * of n_c times the occupancy of its (2R+1)^3 neighbourhood.  Blocks on the
+ * stream (copies one number to the host).
+ */
+int abacus_nf_interactions(abacus_nf_cells cells, void *hip_stream, int64_t *out);
+
+/* Which internal array abacus_nf_copy_cells copies out. */
+typedef enum {
+    ABACUS_NF_ARRAY_PERM = 0,       /* int32 [n_total]: input index of each sorted slot          */
+    ABACUS_NF_ARRAY_CELL_START = 1, /* int32 [n_cells + 1]: first slot of each cell (all boxes)   */
+    ABACUS_NF_ARRAY_SPOS = 2,       /* float32 [n_total][4]: cell-relative x, y, z in cell widths,
+                                       and the z cell index, per sorted slot                      */
+    ABACUS_NF_ARRAY_CELL_KEY = 3    /* int32 [n_total]: global cell index of each sorted slot     */
+} abacus_nf_array;
+
+/* Number of particles and of cells (all boxes) of a built handle. */
+int abacus_nf_cells_size(abacus_nf_cells cells, int64_t *n_total, int64_t *n_cells);
+
+/*
+ * abacus_nf_copy_cells -- enqueue a device-to-device copy of one internal
+ * array into dst (a device buffer of at least `bytes` bytes, which must
+ * equal the array's size).  For inspection and tests.
+ */
+int abacus_nf_copy_cells(abacus_nf_cells cells, abacus_nf_array which, void *dst, int64_t bytes,
+                         void *hip_stream);
+
+/*
+ * Tuning of the force kernel: the i-tile (sinks per lane), the j-tile (LDS
+ * chunk of staged sources), the source unroll, the lanes that share one sink
+ * in sparse cells, and the split of long source lists.  Zero fields mean
+ * "library default".  The autotuner (abacus_nf_autotune) fills it.
+ */
+typedef struct {
+    int32_t sinks_per_lane;  /* i-tile per lane: 1, 2 or 4                                  */
+    int32_t chunk;           /* j-tile: sources staged per LDS chunk (multiple of 64,
+                                64*unroll <= chunk <= 512)                                   */
+    int32_t unroll;          /* sources in flight per lane: 1, 2 or 4                        */
+    int32_t max_lanes;       /* most lanes sharing one sink (1..64)                          */
+    int32_t part_sources;    /* split a tile's source list into parts of about this many
+                                sources per lane (>= 1024)                                   */
+    int32_t waves_per_cu;    /* persistent-kernel waves per compute unit (0 = occupancy)     */
+    int64_t item_capacity;   /* work-list capacity override (tests); 0 = sized from the batch */
+} abacus_nf_tuning;
+
+/* Set the tuning used by later forces calls on this handle (NULL = defaults). */
+int abacus_nf_set_tuning(abacus_nf_cells cells, const abacus_nf_tuning *tuning);
+
+/* Read the tuning in effect (defaults resolved). */
+int abacus_nf_get_tuning(abacus_nf_cells cells, abacus_nf_tuning *tuning);
+
+/*
+ * abacus_nf_autotune -- time candidate tunings of the force kernel on this
+ * handle's data (each candidate runs `reps` times on the stream; blocking)
+ * and keep the fastest.  If cache_path is not NULL the choice is looked up
+ * in, and recorded to, that JSON file under a key made of the device name,
+ * kind, mode and a size class of the batch.  acc receives the forces of the
+ * last run.  The chosen tuning is stored in the handle and, if out is not
+ * NULL, returned.
+ */
+int abacus_nf_autotune(abacus_nf_cells cells, const double *eps, abacus_nf_kind kind, const double *gm,
+                       abacus_nf_sum mode, float *acc, void *hip_stream, int32_t reps,
+                       const char *cache_path, abacus_nf_tuning *out);
+
+/*
+ * Per-stage timing with HIP events recorded on the caller's stream around the
+ * stages of build_cells and forces (off by default).  abacus_nf_last_times
+ * blocks until the last recorded events complete and returns milliseconds of:
+ * [0] build_cells, [1] forces work list, [2] the pairwise force kernel,
+ * [3] finalize.  Stages not run since timing was enabled read as -1.
+ */
+int abacus_nf_set_timing(abacus_nf_cells cells, int32_t enable);
+int abacus_nf_last_times(abacus_nf_cells cells, float ms[4]);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int abacus_nf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABACUS_NF_H */

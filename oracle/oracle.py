@@ -56,7 +56,7 @@ class Oracle:
         c_i64, c_d, vp, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
         lib.oracle_nf_bin.argtypes = [vp, c_i64, c_d, ci, vp]
         lib.oracle_nf_kernel.argtypes = [vp, c_i64, c_d, ci, vp]
-        lib.oracle_nf_forces.argtypes = [vp, c_i64, c_d, ci, ci, c_d, ci, c_d, vp, c_i64, ci, ci, vp, vp]
+        lib.oracle_nf_forces.argtypes = [vp, c_i64, c_d, ci, ci, c_d, ci, c_d, vp, c_i64, ci, ci, vp, vp, vp]
         lib.oracle_nf_count_pairs.argtypes = [vp, c_i64, c_d, ci, ci, vp]
         for f in (lib.oracle_nf_bin, lib.oracle_nf_kernel, lib.oracle_nf_forces, lib.oracle_nf_count_pairs):
             f.restype = ctypes.c_int
@@ -79,8 +79,10 @@ class Oracle:
 
     def forces(self, pos, box: float, K: int, R: int, eps: float, kind: int = SPLINE, gm: float = 1.0,
                sinks: Optional[np.ndarray] = None, neumaier: bool = False, threads: int = 0,
-               return_pairs: bool = False):
-        """FP64 near-field accelerations [m,3] of the sinks (all particles by default)."""
+               return_pairs: bool = False, return_mag: bool = False):
+        """FP64 near-field accelerations [m,3] of the sinks (all particles by default).
+
+        With return_mag, also the per-sink sum of pair-term magnitudes (G*m * sum |d| g)."""
         p = _pos32(pos)
         n = p.shape[0]
         if sinks is None:
@@ -89,12 +91,19 @@ class Oracle:
             sk = np.ascontiguousarray(sinks, dtype=np.int64)
             m, sp = sk.size, sk.ctypes.data
         acc = np.zeros((m, 3), dtype=np.float64)
+        mag = np.zeros(m, dtype=np.float64) if return_mag else None
         pairs = ctypes.c_int64(0)
         rc = self.lib.oracle_nf_forces(p.ctypes.data if n else None, n, float(box), int(K), int(R), float(eps),
                                        int(kind), float(gm), sp, m, int(bool(neumaier)), int(threads),
-                                       acc.ctypes.data if m else None, ctypes.byref(pairs))
+                                       acc.ctypes.data if m else None,
+                                       mag.ctypes.data if (return_mag and m) else None, ctypes.byref(pairs))
         _check(rc, "forces")
-        return (acc, int(pairs.value)) if return_pairs else acc
+        out = [acc]
+        if return_pairs:
+            out.append(int(pairs.value))
+        if return_mag:
+            out.append(mag)
+        return out[0] if len(out) == 1 else tuple(out)
 
     def count_pairs(self, pos, box: float, K: int, R: int = 2) -> int:
         """Exact number of (sink, source) pairs, self pairs included, from cell occupancy."""
@@ -125,8 +134,9 @@ def kernel_g(r, eps, kind=SPLINE):
     return default().kernel_g(r, eps, kind)
 
 
-def forces(pos, box, K, R, eps, kind=SPLINE, gm=1.0, sinks=None, neumaier=False, threads=0, return_pairs=False):
-    return default().forces(pos, box, K, R, eps, kind, gm, sinks, neumaier, threads, return_pairs)
+def forces(pos, box, K, R, eps, kind=SPLINE, gm=1.0, sinks=None, neumaier=False, threads=0, return_pairs=False,
+           return_mag=False):
+    return default().forces(pos, box, K, R, eps, kind, gm, sinks, neumaier, threads, return_pairs, return_mag)
 
 
 def count_pairs(pos, box, K, R=2):

@@ -113,12 +113,15 @@ static inline void neumaier_add(double *s, double *c, double v) {
  * when sinks == NULL), one periodic box.
  *   pos   [n][3] float32, any finite values (wrapped into [0,L) by the cell rule)
  *   acc   [nsinks][3] float64 out, in the order of `sinks`
+ *   mag   [nsinks] float64 out or NULL: G*m * sum over the near field of the
+ *         magnitude of each pair term, |d| g(|d|) (the scale of the rounding
+ *         error any summation order of those terms can make)
  *   pairs total number of (sink, source) pairs visited, self pair included
  * Returns 0, or a negative code for bad arguments / allocation failure.
  */
 int oracle_nf_forces(const float *pos, int64_t n, double L, int K, int R, double eps, int kind,
                      double gm, const int64_t *sinks, int64_t nsinks, int neumaier, int nthreads,
-                     double *acc, int64_t *pairs) {
+                     double *acc, double *mag, int64_t *pairs) {
     if (n < 0 || !(L > 0) || R < 1 || K < 2 * R + 1 || !(eps > 0) || (kind != 0 && kind != 1))
         return ORACLE_EINVAL;
     if (sinks == NULL) nsinks = n;
@@ -157,12 +160,14 @@ int oracle_nf_forces(const float *pos, int64_t n, double L, int K, int R, double
         int64_t i = sinks ? sinks[q] : q;
         if (i < 0 || i >= n) {  /* out-of-range sink: report NaN */
             acc[3 * q] = acc[3 * q + 1] = acc[3 * q + 2] = NAN;
+            if (mag) mag[q] = NAN;
             continue;
         }
         int ci = cell[i];
         int cz = ci % K, cy = (ci / K) % K, cx = ci / (K * K);
         double xi = xt[3 * i], yi = xt[3 * i + 1], zi = xt[3 * i + 2];
         acc3 a = {0, 0, 0, 0, 0, 0};
+        double m = 0.0;
         for (int dx = -R; dx <= R; dx++) {
             int ex = cx + dx, sx = 0;
             if (ex < 0) { ex += K; sx = -1; } else if (ex >= K) { ex -= K; sx = 1; }
@@ -182,6 +187,7 @@ int oracle_nf_forces(const float *pos, int64_t n, double L, int K, int R, double
                         total_pairs++;
                         if (r2 == 0.0) continue;
                         double g = kernel_g(r2, eps, kind);
+                        if (mag) m += sqrt(r2) * g;
                         if (neumaier) {
                             neumaier_add(&a.s0, &a.c0, ddx * g);
                             neumaier_add(&a.s1, &a.c1, ddy * g);
@@ -198,6 +204,7 @@ int oracle_nf_forces(const float *pos, int64_t n, double L, int K, int R, double
         acc[3 * q + 0] = gm * (a.s0 + a.c0);
         acc[3 * q + 1] = gm * (a.s1 + a.c1);
         acc[3 * q + 2] = gm * (a.s2 + a.c2);
+        if (mag) mag[q] = gm * m;
     }
     if (pairs) *pairs = total_pairs;
     free(cell); free(xt); free(start); free(list); free(fill);

@@ -1,0 +1,517 @@
+// C ABI of libabacus_nf: argument checks, buffer management, and the launch
+// sequence of each entry point.  Every argument check runs before the first
+// HIP call, so invalid calls fail synchronously without touching the device.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nf_internal.h"
+
+using namespace anf;
+
+struct abacus_nf_cells_s {
+    int device = -1;
+    int64_t n_total = 0, n_cells = 0;
+    int32_t n_boxes = 0, R = 2;
+    bool built = false;
+    std::vector<abacus_nf_box> boxes;
+    std::vector<int32_t> cell_base;
+    abacus_nf_tuning tune{};
+
+    // capacities (elements)
+    int64_t cap_n = -1, cap_cells = -1, cap_boxes = -1;
+    int32_t *keys_a = nullptr, *vals_a = nullptr, *keys_b = nullptr, *vals_b = nullptr;
+    int32_t *keys = nullptr, *perm = nullptr;  // sorted results (point into the buffers above)
+    float4 *spos = nullptr;
+    int32_t *cell_start = nullptr;
+    int32_t *endpos = nullptr;
+    void *radix_temp = nullptr;
+    void *scan_temp = nullptr;
+    BoxDev *d_boxes = nullptr;
+
+    // force work buffers
+    int64_t wcap_cells = -1, wcap_items = -1, wcap_partials = -1, wcap_boxes = -1;
+    ForceBox *d_fbox = nullptr;
+    WorkState *ws = nullptr;
+    Item *items = nullptr;
+    int32_t *cell_nsrc = nullptr, *cell_parts = nullptr;
+    int64_t *cell_pdem = nullptr, *cell_pbase = nullptr;
+    double *partials = nullptr;
+    void *wscan_temp = nullptr;
+
+    // optional stage timing: event pairs for build, work list, kernel, finalize
+    bool timing = false;
+    hipEvent_t ev[8] = {nullptr};
+    bool ev_used[4] = {false, false, false, false};
+};
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_err_mutex;
+int *g_err[kMaxDevices] = {nullptr};
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) hipFree((void *)p);
+    p = nullptr;
+}
+
+template <typename T>
+bool dalloc(T *&p, size_t count) {
+    dfree(p);
+    if (count == 0) count = 1;
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    p = (T *)q;
+    return true;
+}
+
+bool dalloc_bytes(void *&p, size_t bytes) {
+    if (p) hipFree(p);
+    p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return false;
+    }
+    return true;
+}
+
+void free_sort_buffers(abacus_nf_cells_s *h) {
+    dfree(h->keys_a); dfree(h->vals_a); dfree(h->keys_b); dfree(h->vals_b);
+    dfree(h->spos); dfree(h->cell_start); dfree(h->endpos); dfree(h->d_boxes);
+    if (h->radix_temp) hipFree(h->radix_temp);
+    if (h->scan_temp) hipFree(h->scan_temp);
+    h->radix_temp = h->scan_temp = nullptr;
+    h->keys = h->perm = nullptr;
+    h->cap_n = h->cap_cells = h->cap_boxes = -1;
+}
+
+void destroy_events(abacus_nf_cells_s *h) {
+    for (int i = 0; i < 8; i++)
+        if (h->ev[i]) hipEventDestroy(h->ev[i]);
+    for (int i = 0; i < 8; i++) h->ev[i] = nullptr;
+    for (int i = 0; i < 4; i++) h->ev_used[i] = false;
+}
+
+void mark(abacus_nf_cells_s *h, int stage, bool end, hipStream_t st) {
+    if (!h->timing || !h->ev[2 * stage + (end ? 1 : 0)]) return;
+    hipEventRecord(h->ev[2 * stage + (end ? 1 : 0)], st);
+    if (end) h->ev_used[stage] = true;
+}
+
+void free_work_buffers(abacus_nf_cells_s *h) {
+    dfree(h->d_fbox); dfree(h->ws); dfree(h->items); dfree(h->cell_nsrc); dfree(h->cell_parts);
+    dfree(h->cell_pdem); dfree(h->cell_pbase); dfree(h->partials);
+    if (h->wscan_temp) hipFree(h->wscan_temp);
+    h->wscan_temp = nullptr;
+    h->wcap_cells = h->wcap_items = h->wcap_partials = h->wcap_boxes = -1;
+}
+
+int key_bits(int64_t n_cells) {
+    int b = 0;
+    while (((int64_t)1 << b) < n_cells) b++;
+    return b;
+}
+
+abacus_nf_tuning default_tuning() {
+    abacus_nf_tuning t;
+    memset(&t, 0, sizeof(t));
+    t.sinks_per_lane = 2;
+    t.chunk = 256;
+    t.unroll = 2;
+    t.max_lanes = 64;
+    t.part_sources = 1 << 16;
+    t.waves_per_cu = 0;
+    t.item_capacity = 0;
+    return t;
+}
+
+// Resolve zero fields to defaults; return false if a field is out of range.
+bool resolve_tuning(const abacus_nf_tuning *in, abacus_nf_tuning *out) {
+    abacus_nf_tuning d = default_tuning();
+    abacus_nf_tuning t = in ? *in : d;
+    if (!t.sinks_per_lane) t.sinks_per_lane = d.sinks_per_lane;
+    if (!t.chunk) t.chunk = d.chunk;
+    if (!t.unroll) t.unroll = d.unroll;
+    if (!t.max_lanes) t.max_lanes = d.max_lanes;
+    if (!t.part_sources) t.part_sources = d.part_sources;
+    if (t.sinks_per_lane != 1 && t.sinks_per_lane != 2 && t.sinks_per_lane != 4) return false;
+    if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) return false;
+    if (t.chunk % 64 != 0 || t.chunk < 64 * t.unroll || t.chunk > 512) return false;
+    if (t.max_lanes < 1 || t.max_lanes > 64) return false;
+    if (t.part_sources < 1024) return false;
+    if (t.waves_per_cu < 0 || t.waves_per_cu > 64) return false;
+    if (t.item_capacity < 0 || t.item_capacity >= INT32_MAX) return false;
+    *out = t;
+    return true;
+}
+
+int hip_fail(hipError_t e) {
+    (void)e;
+    (void)hipGetLastError();
+    return ABACUS_NF_EDEVICE;
+}
+
+}  // namespace
+
+namespace anf {
+
+int *device_error_word(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_err_mutex);
+    if (!g_err[device]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (hipMemset(p, 0, sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            hipFree(p);
+            return nullptr;
+        }
+        g_err[device] = (int *)p;
+    }
+    return g_err[device];
+}
+
+}  // namespace anf
+
+extern "C" {
+
+int abacus_nf_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+const char *abacus_nf_strerror(int code) {
+    switch (code) {
+        case ABACUS_NF_OK: return "ok";
+        case ABACUS_NF_EINVAL: return "invalid argument";
+        case ABACUS_NF_ENOMEM: return "out of memory";
+        case ABACUS_NF_EDEVICE: return "HIP runtime error";
+        case ABACUS_NF_ECAPACITY: return "device work list outgrew its capacity";
+        case ABACUS_NF_ENONFINITE: return "non-finite particle position";
+        case ABACUS_NF_ESTATE: return "handle used in the wrong state";
+        default: return "unknown error code";
+    }
+}
+
+int abacus_nf_build_cells(const float *pos, int64_t n_total, const abacus_nf_box *boxes, int32_t n_boxes,
+                          int32_t R, void *hip_stream, abacus_nf_cells *cells) {
+    // ---- argument checks (no HIP call before this block ends)
+    if (!cells || !boxes) return ABACUS_NF_EINVAL;
+    if (n_total < 0 || n_total >= INT32_MAX) return ABACUS_NF_EINVAL;
+    if (n_total > 0 && !pos) return ABACUS_NF_EINVAL;
+    if (n_boxes < 1 || n_boxes > 65536) return ABACUS_NF_EINVAL;
+    if (R < 1 || R > 3) return ABACUS_NF_EINVAL;
+    std::vector<int32_t> base((size_t)n_boxes);
+    int64_t off = 0, cells_total = 0;
+    for (int b = 0; b < n_boxes; b++) {
+        const abacus_nf_box &x = boxes[b];
+        if (x.offset != off || x.n < 0 || x.reserved != 0) return ABACUS_NF_EINVAL;
+        if (!(x.box > 0) || !std::isfinite(x.box)) return ABACUS_NF_EINVAL;
+        if (x.K < 2 * R + 1 || x.K > 1290) return ABACUS_NF_EINVAL;
+        off += x.n;
+        base[b] = (int32_t)cells_total;
+        cells_total += (int64_t)x.K * x.K * x.K;
+        if (cells_total >= INT32_MAX) return ABACUS_NF_EINVAL;
+    }
+    if (off != n_total) return ABACUS_NF_EINVAL;
+
+    // ---- buffers
+    hipStream_t st = (hipStream_t)hip_stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    int *err = device_error_word(dev);
+    if (!err) return ABACUS_NF_ENOMEM;
+    abacus_nf_cells_s *h = *cells;
+    bool fresh = false;
+    if (!h) {
+        h = new (std::nothrow) abacus_nf_cells_s();
+        if (!h) return ABACUS_NF_ENOMEM;
+        h->tune = default_tuning();
+        fresh = true;
+    } else if (h->device != dev) {
+        return ABACUS_NF_ESTATE;
+    }
+    h->device = dev;
+    const int64_t n = n_total;
+    if (h->cap_n < n || h->cap_cells < cells_total || h->cap_boxes < n_boxes) {
+        free_sort_buffers(h);
+        const int64_t cn = std::max<int64_t>(n, 1), cc = std::max<int64_t>(cells_total, 1);
+        bool ok = dalloc(h->keys_a, cn) && dalloc(h->vals_a, cn) && dalloc(h->keys_b, cn) &&
+                  dalloc(h->vals_b, cn) && dalloc(h->spos, cn) && dalloc(h->cell_start, cc + 1) &&
+                  dalloc(h->endpos, cc) && dalloc(h->d_boxes, n_boxes) &&
+                  dalloc_bytes(h->radix_temp, radix_temp_bytes(cn)) &&
+                  dalloc_bytes(h->scan_temp, scan_temp_bytes(std::max(cc, cn)));
+        if (!ok) {
+            free_sort_buffers(h);
+            if (fresh) delete h;
+            return ABACUS_NF_ENOMEM;
+        }
+        h->cap_n = cn;
+        h->cap_cells = cc;
+        h->cap_boxes = n_boxes;
+    }
+    h->n_total = n;
+    h->n_cells = cells_total;
+    h->n_boxes = n_boxes;
+    h->R = R;
+    h->boxes.assign(boxes, boxes + n_boxes);
+    h->cell_base = base;
+    h->built = false;
+    *cells = h;
+
+    // ---- enqueue
+    mark(h, 0, false, st);
+    hipError_t e = launch_set_boxes(boxes, n_boxes, base.data(), h->d_boxes, st);
+    if (e == hipSuccess) e = launch_bin(pos, n, h->d_boxes, n_boxes, h->keys_a, h->vals_a, err, st);
+    int32_t *ks = h->keys_a, *vs = h->vals_a;
+    if (e == hipSuccess)
+        e = radix_sort_pairs(h->keys_a, h->vals_a, h->keys_b, h->vals_b, h->radix_temp, n, key_bits(cells_total), st,
+                             &ks, &vs);
+    if (e == hipSuccess) e = launch_cell_start(ks, n, cells_total, h->endpos, h->cell_start, h->scan_temp, st);
+    if (e == hipSuccess) e = launch_gather(pos, vs, ks, n, h->d_boxes, n_boxes, h->spos, st);
+    if (e != hipSuccess) return hip_fail(e);
+    mark(h, 0, true, st);
+    h->keys = ks;
+    h->perm = vs;
+    h->built = true;
+    return ABACUS_NF_OK;
+}
+
+static int check_force_args(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                            abacus_nf_sum mode, float *acc) {
+    if (!h || !eps || !gm) return ABACUS_NF_EINVAL;
+    if (kind != ABACUS_NF_SPLINE && kind != ABACUS_NF_PLUMMER) return ABACUS_NF_EINVAL;
+    if (mode != ABACUS_NF_SUM_FP32 && mode != ABACUS_NF_SUM_COMP32 && mode != ABACUS_NF_SUM_FP64)
+        return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    if (h->n_total > 0 && !acc) return ABACUS_NF_EINVAL;
+    for (int b = 0; b < h->n_boxes; b++) {
+        const double w = h->boxes[b].box / h->boxes[b].K;
+        if (!std::isfinite(eps[b]) || !std::isfinite(gm[b])) return ABACUS_NF_EINVAL;
+        const double ec = eps[b] / w;
+        if (!(ec >= 1e-5 && ec <= 1.0)) return ABACUS_NF_EINVAL;
+        if (!std::isfinite(gm[b] / (w * w))) return ABACUS_NF_EINVAL;
+    }
+    return ABACUS_NF_OK;
+}
+
+static int ensure_work_buffers(abacus_nf_cells_s *h) {
+    const int64_t n = std::max<int64_t>(h->n_total, 1);
+    const int64_t nc = std::max<int64_t>(h->n_cells, 1);
+    const int64_t want_items = h->tune.item_capacity > 0
+                                   ? h->tune.item_capacity
+                                   : std::min<int64_t>(INT32_MAX - 1, std::min(n, nc) + n / 16 + (1 << 16));
+    const int64_t want_partials = 2 * n + (1 << 16);
+    if (h->wcap_cells >= nc && h->wcap_items == want_items && h->wcap_partials >= want_partials &&
+        h->wcap_boxes >= h->n_boxes)
+        return ABACUS_NF_OK;
+    free_work_buffers(h);
+    bool ok = dalloc(h->d_fbox, h->n_boxes) && dalloc(h->ws, 1) && dalloc(h->items, want_items) &&
+              dalloc(h->cell_nsrc, nc) && dalloc(h->cell_parts, nc) && dalloc(h->cell_pdem, nc) &&
+              dalloc(h->cell_pbase, nc) && dalloc(h->partials, 3 * want_partials) &&
+              dalloc_bytes(h->wscan_temp, scan_temp_bytes(nc));
+    if (!ok) {
+        free_work_buffers(h);
+        return ABACUS_NF_ENOMEM;
+    }
+    h->wcap_cells = nc;
+    h->wcap_items = want_items;
+    h->wcap_partials = want_partials;
+    h->wcap_boxes = h->n_boxes;
+    return ABACUS_NF_OK;
+}
+
+static ForcesArgs make_args(abacus_nf_cells_s *h, abacus_nf_kind kind, abacus_nf_sum mode, float *acc, int *err) {
+    ForcesArgs a;
+    memset(&a, 0, sizeof(a));
+    a.spos = h->spos;
+    a.cell_start = h->cell_start;
+    a.perm = h->perm;
+    a.keys = h->keys;
+    a.boxes = h->d_boxes;
+    a.fbox = h->d_fbox;
+    a.n_boxes = h->n_boxes;
+    a.n_total = h->n_total;
+    a.n_cells = h->n_cells;
+    a.R = h->R;
+    a.items = h->items;
+    a.item_capacity = h->wcap_items;
+    a.ws = h->ws;
+    a.cell_nsrc = h->cell_nsrc;
+    a.cell_parts = h->cell_parts;
+    a.cell_pdem = h->cell_pdem;
+    a.cell_pbase = h->cell_pbase;
+    a.partials = h->partials;
+    a.partial_capacity = h->wcap_partials;
+    a.acc = acc;
+    a.err = err;
+    a.kind = kind;
+    a.mode = mode;
+    a.tune = h->tune;
+    a.scan_temp = h->wscan_temp;
+    return a;
+}
+
+int abacus_nf_forces(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                     abacus_nf_sum mode, float *acc, void *hip_stream) {
+    int rc = check_force_args(h, eps, kind, gm, mode, acc);
+    if (rc != ABACUS_NF_OK) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (dev != h->device) return ABACUS_NF_ESTATE;
+    int *err = device_error_word(dev);
+    if (!err) return ABACUS_NF_ENOMEM;
+    if ((rc = ensure_work_buffers(h)) != ABACUS_NF_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (h->n_total == 0) return ABACUS_NF_OK;
+    ForcesArgs a = make_args(h, kind, mode, acc, err);
+    a.grid = forces_grid(h->tune, kind, mode, dev);
+    mark(h, 1, false, st);
+    hipError_t e = launch_set_force_boxes(eps, gm, h->boxes.data(), h->n_boxes, h->d_fbox, st);
+    if (e == hipSuccess) e = build_work_list(a, st);
+    mark(h, 1, true, st);
+    mark(h, 2, false, st);
+    if (e == hipSuccess) e = launch_forces(a, st);
+    mark(h, 2, true, st);
+    mark(h, 3, false, st);
+    if (e == hipSuccess) e = launch_finalize(a, st);
+    mark(h, 3, true, st);
+    if (e != hipSuccess) return hip_fail(e);
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_sync(void *hip_stream) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (hipStreamSynchronize(st) != hipSuccess) return hip_fail(hipErrorUnknown);
+    int *err = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_err_mutex);
+        if (dev >= 0 && dev < kMaxDevices) err = g_err[dev];
+    }
+    if (!err) return ABACUS_NF_OK;
+    int v = 0;
+    if (hipMemcpy(&v, err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (v != 0) {
+        if (hipMemset(err, 0, sizeof(int)) != hipSuccess) return hip_fail(hipErrorUnknown);
+        return v;
+    }
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_free_cells(abacus_nf_cells h) {
+    if (!h) return ABACUS_NF_OK;
+    int rc = ABACUS_NF_OK;
+    if (h->device >= 0) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && cur != h->device) hipSetDevice(h->device);
+        if (hipDeviceSynchronize() != hipSuccess) rc = hip_fail(hipErrorUnknown);
+        free_sort_buffers(h);
+        free_work_buffers(h);
+        destroy_events(h);
+        if (cur != h->device) hipSetDevice(cur);
+    }
+    delete h;
+    return rc;
+}
+
+int abacus_nf_interactions(abacus_nf_cells h, void *hip_stream, int64_t *out) {
+    if (!h || !out) return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (dev != h->device) return ABACUS_NF_ESTATE;
+    int rc = ensure_work_buffers(h);
+    if (rc != ABACUS_NF_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    ForcesArgs a = make_args(h, ABACUS_NF_SPLINE, ABACUS_NF_SUM_FP32, nullptr, device_error_word(dev));
+    hipError_t e = launch_count_interactions(a, st);
+    if (e != hipSuccess) return hip_fail(e);
+    unsigned long long v = 0;
+    if (hipMemcpyAsync(&v, &h->ws->interactions, sizeof(v), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_fail(hipErrorUnknown);
+    *out = (int64_t)v;
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_cells_size(abacus_nf_cells h, int64_t *n_total, int64_t *n_cells) {
+    if (!h || !n_total || !n_cells) return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    *n_total = h->n_total;
+    *n_cells = h->n_cells;
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_copy_cells(abacus_nf_cells h, abacus_nf_array which, void *dst, int64_t bytes, void *hip_stream) {
+    if (!h || !dst) return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    const void *src = nullptr;
+    int64_t want = 0;
+    switch (which) {
+        case ABACUS_NF_ARRAY_PERM: src = h->perm; want = h->n_total * 4; break;
+        case ABACUS_NF_ARRAY_CELL_START: src = h->cell_start; want = (h->n_cells + 1) * 4; break;
+        case ABACUS_NF_ARRAY_SPOS: src = h->spos; want = h->n_total * 16; break;
+        case ABACUS_NF_ARRAY_CELL_KEY: src = h->keys; want = h->n_total * 4; break;
+        default: return ABACUS_NF_EINVAL;
+    }
+    if (bytes != want) return ABACUS_NF_EINVAL;
+    if (want == 0) return ABACUS_NF_OK;
+    if (hipMemcpyAsync(dst, src, (size_t)want, hipMemcpyDeviceToDevice, (hipStream_t)hip_stream) != hipSuccess)
+        return hip_fail(hipErrorUnknown);
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_set_timing(abacus_nf_cells h, int32_t enable) {
+    if (!h || h->device < 0) return ABACUS_NF_EINVAL;
+    if (enable && !h->ev[0]) {
+        for (int i = 0; i < 8; i++)
+            if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+                destroy_events(h);
+                return hip_fail(hipErrorUnknown);
+            }
+    }
+    for (int i = 0; i < 4; i++) h->ev_used[i] = false;
+    h->timing = enable != 0;
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_last_times(abacus_nf_cells h, float ms[4]) {
+    if (!h || !ms) return ABACUS_NF_EINVAL;
+    for (int i = 0; i < 4; i++) {
+        ms[i] = -1.f;
+        if (!h->ev_used[i]) continue;
+        if (hipEventSynchronize(h->ev[2 * i + 1]) != hipSuccess) return hip_fail(hipErrorUnknown);
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) return hip_fail(hipErrorUnknown);
+        ms[i] = t;
+    }
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_set_tuning(abacus_nf_cells h, const abacus_nf_tuning *tuning) {
+    if (!h) return ABACUS_NF_EINVAL;
+    abacus_nf_tuning t;
+    if (!resolve_tuning(tuning, &t)) return ABACUS_NF_EINVAL;
+    h->tune = t;
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_get_tuning(abacus_nf_cells h, abacus_nf_tuning *tuning) {
+    if (!h || !tuning) return ABACUS_NF_EINVAL;
+    *tuning = h->tune;
+    return ABACUS_NF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Autotuner of the force kernel: times candidate i/j tiles, unrolls and lane
+// sharing on the handle's own data and keeps the fastest.  Choices can be
+// cached in a small JSON file keyed by device, kind, mode and a size class.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "nf_internal.h"
+
+namespace {
+
+std::string cache_key(abacus_nf_cells h, abacus_nf_kind kind, abacus_nf_sum mode) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    std::string name = "gpu";
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) name = p.gcnArchName;
+    for (char &c : name)
+        if (c == '"' || c == '\\' || c == ':') c = '_';
+    int64_t n = 0, nc = 0;
+    abacus_nf_cells_size(h, &n, &nc);
+    const double per_cell = nc > 0 ? (double)n / (double)nc : 0.0;
+    const int size_class = n > 0 ? (int)std::floor(std::log2((double)n)) : 0;
+    const int occ_class = per_cell > 0 ? (int)std::floor(std::log2(per_cell) * 2) : -99;
+    std::ostringstream k;
+    k << name << "|k" << (int)kind << "|m" << (int)mode << "|n" << size_class << "|o" << occ_class;
+    return k.str();
+}
+
+// The cache file is a flat JSON object: {"key": [S, chunk, unroll, max_lanes, part_sources], ...}
+std::map<std::string, std::vector<long long>> read_cache(const char *path) {
+    std::map<std::string, std::vector<long long>> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        std::string key = s.substr(i + 1, j - i - 1);
+        size_t a = s.find('[', j), b = s.find(']', j);
+        if (a == std::string::npos || b == std::string::npos || b < a) break;
+        std::vector<long long> v;
+        std::stringstream vs(s.substr(a + 1, b - a - 1));
+        std::string tok;
+        while (std::getline(vs, tok, ',')) v.push_back(std::atoll(tok.c_str()));
+        m[key] = v;
+        i = b + 1;
+    }
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, std::vector<long long>> &m) {
+    std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        f << "{\n";
+        size_t k = 0;
+        for (auto &kv : m) {
+            f << "  \"" << kv.first << "\": [";
+            for (size_t q = 0; q < kv.second.size(); q++) f << (q ? ", " : "") << kv.second[q];
+            f << "]" << (++k < m.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                                  abacus_nf_sum mode, float *acc, void *hip_stream, int32_t reps,
+                                  const char *cache_path, abacus_nf_tuning *out) {
+    if (!h || reps < 1 || reps > 100) return ABACUS_NF_EINVAL;
+    abacus_nf_tuning cur;
+    int rc = abacus_nf_get_tuning(h, &cur);
+    if (rc) return rc;
+    const std::string key = cache_key(h, kind, mode);
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        auto it = m.find(key);
+        if (it != m.end() && it->second.size() == 5) {
+            abacus_nf_tuning t = cur;
+            t.sinks_per_lane = (int32_t)it->second[0];
+            t.chunk = (int32_t)it->second[1];
+            t.unroll = (int32_t)it->second[2];
+            t.max_lanes = (int32_t)it->second[3];
+            t.part_sources = (int32_t)it->second[4];
+            if (abacus_nf_set_tuning(h, &t) == ABACUS_NF_OK) {
+                rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+                if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
+                if (rc == ABACUS_NF_OK && out) abacus_nf_get_tuning(h, out);
+                return rc;
+            }
+        }
+    }
+    std::vector<abacus_nf_tuning> cand;
+    for (int S : {1, 2, 4})
+        for (int U : {1, 2, 4})
+            for (int chunk : {256, 512})
+                for (int ml : {8, 64}) {
+                    abacus_nf_tuning t = cur;
+                    t.sinks_per_lane = S;
+                    t.unroll = U;
+                    t.chunk = chunk;
+                    t.max_lanes = ml;
+                    cand.push_back(t);
+                }
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return ABACUS_NF_EDEVICE;
+    float best = 1e30f;
+    abacus_nf_tuning best_t = cur;
+    for (const abacus_nf_tuning &t : cand) {
+        if (abacus_nf_set_tuning(h, &t) != ABACUS_NF_OK) continue;
+        rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);  // warm-up (allocates if needed)
+        if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
+        if (rc != ABACUS_NF_OK) break;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < reps && rc == ABACUS_NF_OK; r++) rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+        hipEventRecord(e1, st);
+        if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
+        if (rc != ABACUS_NF_OK) break;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != ABACUS_NF_OK) {
+        abacus_nf_set_tuning(h, &cur);
+        return rc;
+    }
+    abacus_nf_set_tuning(h, &best_t);
+    rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+    if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
+    if (rc != ABACUS_NF_OK) return rc;
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        m[key] = {best_t.sinks_per_lane, best_t.chunk, best_t.unroll, best_t.max_lanes, best_t.part_sources};
+        write_cache(cache_path, m);
+    }
+    if (out) abacus_nf_get_tuning(h, out);
+    return ABACUS_NF_OK;
+}

@@ -1,0 +1,790 @@
+// Near-field force: device work list and the persistent pairwise kernel.
+//
+// The operation is the direct sum of Sec. 3.1 (near field = cells within R,
+// explicit periodic images) with the spline or Plummer softening of Sec. 2.4
+// and Sec. 5.2.  The paper runs it as CUDA kernels on host-packaged work units
+// ("Index Near Force Pencils", "spatially compact GPU work units", Sec. 4.3 and
+// Sec. 4.5).  Here the work list is built on the device and one persistent
+// launch drains it:
+//
+//   k_wl_cells    per cell: occupancy n_c, near-field source count, pair total
+//   k_wl_plan     scales the source-part length so partial slots fit
+//   k_wl_count    per cell: tiles x parts, cost class (histogram over classes)
+//   k_wl_classes  class offsets (heaviest items first), capacity checks
+//   k_wl_emit     items written in class order
+//   k_forces      persistent waves pop items: sink tile in VGPRs, sources staged
+//                 through the wave's LDS region with the periodic cell offset
+//                 applied, FP32 pair math, FP32 / two-sum / FP64 accumulation,
+//                 ordered cross-lane reduction, output in input order
+//   k_finalize    sums the parts of sinks whose source list was split (FP64)
+//
+// Numbers are in cell-width units: positions are relative to the sink cell's
+// centre, so the pair terms need no large-coordinate cancellation.
+#include <climits>
+#include <cstring>
+#include <cmath>
+
+#include "nf_internal.h"
+
+namespace anf {
+
+namespace {
+
+constexpr int kWaves = 4;                 // independent waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr float kTiny = 1e-20f;           // keeps rsqrt finite for coincident pairs
+constexpr float kFar = 1e18f;             // padding source: its terms underflow to exactly 0
+
+inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// ---------------------------------------------------------------- per-box constants
+
+constexpr int kFBoxChunk = 48;
+struct FBoxChunk {
+    ForceBox f[kFBoxChunk];
+    int first, count;
+};
+
+__global__ void k_set_fbox(FBoxChunk c, ForceBox *dst) {
+    int i = threadIdx.x;
+    if (i < c.count) dst[c.first + i] = c.f[i];
+}
+
+// ---------------------------------------------------------------- near-field columns
+
+// The near field of cell (cx, cy, cz) is (2R+1)^2 columns of neighbouring
+// cells, each a run of 2R+1 consecutive cells along z.  In the sorted layout
+// a run is a contiguous slot range, split in two where it wraps through the
+// periodic z boundary.  czref turns the stored z cell index of a source into
+// its offset from the sink cell: dz = cz_src - czref.
+struct ColSeg {
+    int32_t src0, len0, src1, len1;
+    float czref0, czref1;
+};
+
+__device__ inline void column_segments(const int32_t *__restrict__ cs, int colbase, int cz, int K, int R,
+                                       ColSeg &o) {
+    const int z0 = cz - R, z1 = cz + R;
+    if (z0 < 0) {            // images below the box first, then the cells from 0
+        o.src0 = cs[colbase + z0 + K];
+        o.len0 = cs[colbase + K] - o.src0;
+        o.czref0 = (float)(cz + K);
+        o.src1 = cs[colbase];
+        o.len1 = cs[colbase + z1 + 1] - o.src1;
+        o.czref1 = (float)cz;
+    } else if (z1 >= K) {    // cells up to K-1, then images above the box
+        o.src0 = cs[colbase + z0];
+        o.len0 = cs[colbase + K] - o.src0;
+        o.czref0 = (float)cz;
+        o.src1 = cs[colbase];
+        o.len1 = cs[colbase + z1 - K + 1] - o.src1;
+        o.czref1 = (float)(cz - K);
+    } else {
+        o.src0 = cs[colbase + z0];
+        o.len0 = cs[colbase + z1 + 1] - o.src0;
+        o.czref0 = (float)cz;
+        o.src1 = 0;
+        o.len1 = 0;
+        o.czref1 = 0.f;
+    }
+}
+
+__device__ inline int wrap(int v, int K) { return v < 0 ? v + K : (v >= K ? v - K : v); }
+
+// Number of near-field sources of cell c.
+__device__ inline int cell_sources(const int32_t *__restrict__ cs, const BoxDev &B, int lin, int R) {
+    const int K = B.K;
+    const int cz = lin % K, cy = (lin / K) % K, cx = lin / (K * K);
+    int total = 0;
+    for (int dx = -R; dx <= R; dx++) {
+        const int ex = wrap(cx + dx, K);
+        for (int dy = -R; dy <= R; dy++) {
+            const int ey = wrap(cy + dy, K);
+            ColSeg o;
+            column_segments(cs, B.cell_base + (ex * K + ey) * K, cz, K, R, o);
+            total += o.len0 + o.len1;
+        }
+    }
+    return total;
+}
+
+// Tiles, parts and cost class of one cell.
+struct CellPlan {
+    int tiles, parts, cls;
+    int64_t items;
+};
+
+__device__ inline CellPlan plan_cell(int n, int nsrc, int S, int max_lanes, int part_iters) {
+    CellPlan p;
+    if (n <= 0) {
+        p.tiles = p.parts = 0;
+        p.items = 0;
+        p.cls = kNumClasses - 1;
+        return p;
+    }
+    const TileGeom tg = tile_geom(n, S, max_lanes);
+    p.tiles = (n + tg.cap - 1) / tg.cap;
+    const int64_t iters = ((int64_t)nsrc + tg.L - 1) / tg.L;  // source iterations per lane
+    int64_t parts = (iters + part_iters - 1) / part_iters;
+    if (parts < 1) parts = 1;
+    if (parts > nsrc) parts = nsrc > 0 ? nsrc : 1;
+    p.parts = (int)parts;
+    p.items = (int64_t)p.tiles * p.parts;
+    // cost of one item ~ iterations per lane x sinks per lane; classes are half octaves, heaviest first
+    const double cost = (double)(iters / parts + 1) * S + 16.0;
+    int cls = kNumClasses - 1 - (int)(2.0 * log2(cost));
+    p.cls = cls < 0 ? 0 : (cls >= kNumClasses ? kNumClasses - 1 : cls);
+    return p;
+}
+
+// ---------------------------------------------------------------- work-list kernels
+
+__global__ void k_wl_clear(WorkState *ws, int part_iters) {
+    int t = threadIdx.x;
+    if (t == 0) {
+        ws->interactions = 0;
+        ws->part_demand = 0;
+        ws->base_items = 0;
+        ws->split_items = 0;
+        ws->n_items = 0;
+        ws->cursor = 0;
+        ws->part_iters = part_iters;
+        ws->overflow = 0;
+    }
+    if (t < kNumClasses) {
+        ws->class_count[t] = 0;
+        ws->class_fill[t] = 0;
+        ws->class_base[t] = 0;
+    }
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Per cell: source count, exact pair total, and the demand of the base part length.
+__global__ __launch_bounds__(256) void k_wl_cells(const int32_t *__restrict__ cs, const BoxDev *__restrict__ boxes,
+                                                  int n_boxes, int64_t n_cells, int R, int S, int max_lanes,
+                                                  int32_t *__restrict__ cell_nsrc, WorkState *ws) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long inter = 0, pdem = 0, base_items = 0, split_items = 0;
+    if (c < n_cells) {
+        const int n = cs[c + 1] - cs[c];
+        int nsrc = 0;
+        if (n > 0) {
+            const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, (int32_t)c) : 0;
+            const BoxDev B = boxes[b];
+            nsrc = cell_sources(cs, B, (int)(c - B.cell_base), R);
+            inter = (unsigned long long)n * (unsigned long long)nsrc;
+            const CellPlan p = plan_cell(n, nsrc, S, max_lanes, ws->part_iters);
+            base_items = (unsigned long long)p.tiles;
+            if (p.parts > 1) {
+                pdem = (unsigned long long)p.parts * (unsigned long long)n;
+                split_items = (unsigned long long)p.items;
+            }
+        }
+        cell_nsrc[c] = nsrc;
+    }
+    inter = wave_sum_u64(inter);
+    pdem = wave_sum_u64(pdem);
+    base_items = wave_sum_u64(base_items);
+    split_items = wave_sum_u64(split_items);
+    if ((threadIdx.x & 63) == 0) {
+        if (inter) atomicAdd(&ws->interactions, inter);
+        if (pdem) atomicAdd(&ws->part_demand, pdem);
+        if (base_items) atomicAdd(&ws->base_items, base_items);
+        if (split_items) atomicAdd(&ws->split_items, split_items);
+    }
+}
+
+// Lengthen the source parts until the partial slots and the items fit.
+__global__ void k_wl_plan(WorkState *ws, int64_t partial_capacity, int64_t item_capacity, int64_t n_total) {
+    if (threadIdx.x != 0) return;
+    const int64_t pbudget = partial_capacity - n_total;
+    const int64_t ibudget = item_capacity - (int64_t)ws->base_items;
+    int64_t f = 1;
+    const int64_t pd = (int64_t)ws->part_demand, id = (int64_t)ws->split_items;
+    if (pd > 0) {
+        int64_t fp = pbudget > 0 ? (pd + pbudget - 1) / pbudget : INT_MAX;
+        if (fp > f) f = fp;
+    }
+    if (id > 0) {
+        int64_t fi = ibudget > 0 ? (id + ibudget - 1) / ibudget : INT_MAX;
+        if (fi > f) f = fi;
+    }
+    int64_t it = (int64_t)ws->part_iters * f;
+    ws->part_iters = (int32_t)(it > INT_MAX ? INT_MAX : it);
+}
+
+__global__ __launch_bounds__(256) void k_wl_count(const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_nsrc,
+                                                  int64_t n_cells, int S, int max_lanes, WorkState *ws,
+                                                  int32_t *__restrict__ cell_parts, int64_t *__restrict__ cell_pdem) {
+    __shared__ int32_t hist[kNumClasses];
+    if (threadIdx.x < kNumClasses) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int part_iters = ws->part_iters;
+    if (c < n_cells) {
+        const int n = cs[c + 1] - cs[c];
+        const CellPlan p = plan_cell(n, cell_nsrc[c], S, max_lanes, part_iters);
+        cell_parts[c] = p.parts;
+        cell_pdem[c] = p.parts > 1 ? (int64_t)p.parts * n : 0;
+        if (p.items > 0) atomicAdd(&hist[p.cls], (int32_t)p.items);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses && hist[threadIdx.x]) atomicAdd(&ws->class_count[threadIdx.x], hist[threadIdx.x]);
+}
+
+__global__ void k_wl_classes(WorkState *ws, int64_t item_capacity, const int64_t *__restrict__ pbase,
+                             const int64_t *__restrict__ pdem, int64_t n_cells, int64_t partial_capacity,
+                             int *err) {
+    if (threadIdx.x != 0) return;
+    int64_t run = 0;
+    for (int k = 0; k < kNumClasses; k++) {
+        ws->class_base[k] = (int32_t)(run < INT_MAX ? run : INT_MAX);
+        ws->class_fill[k] = 0;
+        run += ws->class_count[k];
+    }
+    int64_t need_p = n_cells > 0 ? pbase[n_cells - 1] + pdem[n_cells - 1] : 0;
+    bool over = run > item_capacity || need_p > partial_capacity;
+    // on overflow nothing is emitted and nothing is computed: the error is
+    // reported by abacus_nf_sync and the output is left unwritten
+    ws->n_items = over ? 0 : (int32_t)run;
+    ws->cursor = 0;
+    ws->overflow = over ? 1 : 0;
+    if (over) atomicCAS(err, 0, ABACUS_NF_ECAPACITY);
+}
+
+__global__ __launch_bounds__(256) void k_wl_emit(const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_nsrc,
+                                                 const int32_t *__restrict__ cell_parts,
+                                                 const BoxDev *__restrict__ boxes, int n_boxes, int64_t n_cells,
+                                                 int S, int max_lanes, WorkState *ws, Item *__restrict__ items,
+                                                 int64_t item_capacity) {
+    __shared__ int32_t cnt[kNumClasses];
+    __shared__ int32_t bbase[kNumClasses];
+    if (threadIdx.x < kNumClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    CellPlan p;
+    p.items = 0;
+    p.cls = 0;
+    p.tiles = p.parts = 0;
+    int local = 0;
+    if (c < n_cells) {
+        const int n = cs[c + 1] - cs[c];
+        if (n > 0) {
+            p = plan_cell(n, cell_nsrc[c], S, max_lanes, ws->part_iters);
+            p.parts = cell_parts[c];
+            p.items = (int64_t)p.tiles * p.parts;
+            local = atomicAdd(&cnt[p.cls], (int32_t)p.items);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses) {
+        int k = threadIdx.x;
+        bbase[k] = cnt[k] ? atomicAdd(&ws->class_fill[k], cnt[k]) : 0;
+    }
+    __syncthreads();
+    if (p.items > 0 && !ws->overflow) {
+        const int64_t base = (int64_t)ws->class_base[p.cls] + bbase[p.cls] + local;
+        if (base + p.items <= item_capacity) {
+            const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, (int32_t)c) : 0;
+            int64_t k = base;
+            for (int t = 0; t < p.tiles; t++)
+                for (int q = 0; q < p.parts; q++) items[k++] = Item{(int32_t)c, t, q, b};
+        }
+    }
+}
+
+// ---------------------------------------------------------------- the force kernel
+
+struct KArgs {
+    const float4 *spos;
+    const int32_t *cs;
+    const int32_t *perm;
+    const Item *items;
+    WorkState *ws;
+    const BoxDev *boxes;
+    const ForceBox *fbox;
+    const int32_t *cell_parts;
+    const int64_t *cell_pbase;
+    double *partials;
+    float *acc;
+    int R;
+    int chunk;      // sources per LDS chunk
+    int max_lanes;
+    int region;     // bytes of LDS per wave
+};
+
+struct Seg {
+    int32_t src, len, flat;
+    float czref;
+};
+
+// Orders LDS traffic between the lanes of one wave (no other wave takes part).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ inline int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One FP32 pair term: returns g with d = (dx, dy, dz) = source - sink.
+//   spline : g = min(r^-3, c0 + r2 (c1 r^-1 + c2)); the cubic force polynomial
+//            lies below r^-2 inside eps and above it outside, so the minimum
+//            selects the right branch without a compare.
+//   Plummer: g = (r2 + eps2)^(-3/2).
+template <int KIND>
+__device__ __forceinline__ float pair_g(float dx, float dy, float dz, float c0, float c1, float c2, float e2) {
+    if constexpr (KIND == ABACUS_NF_PLUMMER) {
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, e2)));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri2 = ri * ri;
+        return ri2 * ri;
+    } else {
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, kTiny)));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float t = __builtin_fmaf(c1, ri, c2);
+        const float ri2 = ri * ri;
+        const float p = __builtin_fmaf(r2, t, c0);
+        const float ri3 = ri2 * ri;
+        return fminf(ri3, p);
+    }
+}
+
+// Knuth's two-sum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+template <int KIND, int MODE, int S, int U>
+__global__ __launch_bounds__(kThreads) void k_forces(KArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    unsigned char *region = smem + (size_t)wave * a.region;
+    float4 *stage = (float4 *)region;
+    Seg *segs = (Seg *)(region + (size_t)a.chunk * sizeof(float4));
+    double *red = (double *)region;
+    float *redf = (float *)region;
+    const int R = a.R;
+    const int W = 2 * R + 1;
+    const int ncol = W * W;
+    const int n_items = a.ws->n_items;
+
+    for (;;) {
+        int k = 0;
+        if (lane == 0) k = atomicAdd(&a.ws->cursor, 1);
+        k = sgpr(__shfl(k, 0));
+        if (k >= n_items) break;
+        const Item it = a.items[k];
+        const int c = sgpr(it.cell);
+        const int ib = sgpr(it.box);
+        const BoxDev B = a.boxes[ib];
+        const ForceBox F = a.fbox[ib];
+        const int K = B.K;
+        const int lin = c - B.cell_base;
+        const int cz = lin % K, cy = (lin / K) % K, cx = lin / (K * K);
+        const int cs0 = a.cs[c];
+        const int nc = a.cs[c + 1] - cs0;
+        const TileGeom tg = tile_geom(nc, S, a.max_lanes);
+        const int L = tg.L, G = tg.G;
+        const int t0 = sgpr(it.tile) * tg.cap;
+        const int nt = min(tg.cap, nc - t0);
+        const int g = lane / L, sub = lane - g * L;
+
+        // sink tile: S sinks per lane, relative to the sink cell centre
+        float xi[S], yi[S], zi[S];
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const int idx = g * S + s;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (g < G && idx < nt) p = a.spos[cs0 + t0 + idx];
+            xi[s] = p.x;
+            yi[s] = p.y;
+            zi[s] = p.z;
+        }
+
+        // segment table of the near field (one column per lane), flattened by a prefix sum
+        ColSeg o;
+        o.src0 = o.len0 = o.src1 = o.len1 = 0;
+        o.czref0 = o.czref1 = 0.f;
+        if (lane < ncol) {
+            const int ex = wrap(cx + lane / W - R, K), ey = wrap(cy + lane % W - R, K);
+            column_segments(a.cs, B.cell_base + (ex * K + ey) * K, cz, K, R, o);
+        }
+        int incl = o.len0 + o.len1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        const int nsrc = sgpr(__shfl(incl, 63));
+        wave_lds_sync();
+        if (lane < ncol) {
+            const int start = incl - (o.len0 + o.len1);
+            segs[2 * lane] = Seg{o.src0, o.len0, start, o.czref0};
+            segs[2 * lane + 1] = Seg{o.src1, o.len1, start + o.len0, o.czref1};
+        }
+        wave_lds_sync();
+
+        const int P = a.cell_parts[c];
+        const int part = sgpr(it.part);
+        const int j0 = (int)((int64_t)nsrc * part / P);
+        const int j1 = (int)((int64_t)nsrc * (part + 1) / P);
+
+        float ax[S], ay[S], az[S];
+        float hx[S], hy[S], hz[S], lx[S], ly[S], lz[S];
+        double dxs[S], dys[S], dzs[S];
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            ax[s] = ay[s] = az[s] = 0.f;
+            hx[s] = hy[s] = hz[s] = lx[s] = ly[s] = lz[s] = 0.f;
+            dxs[s] = dys[s] = dzs[s] = 0.0;
+        }
+        const float c0 = F.c0, c1 = F.c1, c2 = F.c2, e2 = F.eps2;
+        const int step = L * U;
+        const int nmax = (a.chunk / step) * step;
+
+        int si = 0;
+        for (int f = j0; f < j1;) {
+            const int n = min(nmax, j1 - f);
+            // stage [f, f+n) of the flattened source list, offsets applied
+            int ff = f;
+            while (ff < f + n) {
+                Seg sg = segs[si];
+                int sflat = sgpr(sg.flat), slen = sgpr(sg.len);
+                while (sflat + slen <= ff && si + 1 < 2 * ncol) {
+                    si++;
+                    sg = segs[si];
+                    sflat = sgpr(sg.flat);
+                    slen = sgpr(sg.len);
+                }
+                const int end = min(sflat + slen, f + n);
+                if (end <= ff) break;  // unreachable for a consistent table; guarantees termination
+                const int col = si >> 1;
+                const float offx = (float)(col / W - R), offy = (float)(col % W - R);
+                const float czref = __builtin_bit_cast(float, sgpr(__builtin_bit_cast(int, sg.czref)));
+                const int srcb = sgpr(sg.src) + (ff - sflat);
+                const int cnt = end - ff;
+                float4 *dst = stage + (ff - f);
+                for (int q = lane; q < cnt; q += 64) {
+                    const float4 p = a.spos[srcb + q];
+                    dst[q] = make_float4(p.x + offx, p.y + offy, p.z + (p.w - czref), 0.f);
+                }
+                ff = end;
+            }
+            const int npad = ((n + step - 1) / step) * step;
+            for (int q = n + lane; q < npad; q += 64) stage[q] = make_float4(kFar, kFar, kFar, 0.f);
+            wave_lds_sync();
+
+            if constexpr (MODE == ABACUS_NF_SUM_COMP32) {
+#pragma unroll
+                for (int s = 0; s < S; s++) ax[s] = ay[s] = az[s] = 0.f;
+            }
+            for (int q = sub; q < npad; q += step) {
+                float4 p[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) p[u] = stage[q + u * L];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+#pragma unroll
+                    for (int s = 0; s < S; s++) {
+                        const float dx = p[u].x - xi[s], dy = p[u].y - yi[s], dz = p[u].z - zi[s];
+                        const float gg = pair_g<KIND>(dx, dy, dz, c0, c1, c2, e2);
+                        if constexpr (MODE == ABACUS_NF_SUM_FP64) {
+                            dxs[s] += (double)(dx * gg);
+                            dys[s] += (double)(dy * gg);
+                            dzs[s] += (double)(dz * gg);
+                        } else {
+                            ax[s] = __builtin_fmaf(dx, gg, ax[s]);
+                            ay[s] = __builtin_fmaf(dy, gg, ay[s]);
+                            az[s] = __builtin_fmaf(dz, gg, az[s]);
+                        }
+                    }
+                }
+            }
+            if constexpr (MODE == ABACUS_NF_SUM_COMP32) {
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    float e;
+                    two_sum(hx[s], ax[s], hx[s], e);
+                    lx[s] += e;
+                    two_sum(hy[s], ay[s], hy[s], e);
+                    ly[s] += e;
+                    two_sum(hz[s], az[s], hz[s], e);
+                    lz[s] += e;
+                }
+            }
+            wave_lds_sync();
+            f += n;
+        }
+
+        // ordered reduction over the L lanes that share each sink, one component at a time
+        const int slot0 = cs0 + t0;
+        const bool split = P > 1;
+        const int64_t pb = split ? a.cell_pbase[c] + (int64_t)part * nc + t0 : 0;
+        double tot[S][3];
+        float totf[S][3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                if constexpr (MODE == ABACUS_NF_SUM_FP32) {
+                    redf[lane * S + s] = d == 0 ? ax[s] : (d == 1 ? ay[s] : az[s]);
+                } else if constexpr (MODE == ABACUS_NF_SUM_COMP32) {
+                    const float h = d == 0 ? hx[s] : (d == 1 ? hy[s] : hz[s]);
+                    const float l = d == 0 ? lx[s] : (d == 1 ? ly[s] : lz[s]);
+                    red[lane * S + s] = (double)h + (double)l;
+                } else {
+                    red[lane * S + s] = d == 0 ? dxs[s] : (d == 1 ? dys[s] : dzs[s]);
+                }
+            }
+            wave_lds_sync();
+            if (sub == 0 && g < G) {
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    if constexpr (MODE == ABACUS_NF_SUM_FP32) {
+                        float t = 0.f;
+                        for (int q = 0; q < L; q++) t += redf[(g * L + q) * S + s];
+                        totf[s][d] = t;
+                    } else {
+                        double t = 0.0;
+                        for (int q = 0; q < L; q++) t += red[(g * L + q) * S + s];
+                        tot[s][d] = t;
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+        if (sub == 0 && g < G) {
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                const int idx = g * S + s;
+                if (idx < nt) {
+                    if (!split) {
+                        const int64_t i = a.perm[slot0 + idx];
+                        float *out = a.acc + 3 * i;
+                        if constexpr (MODE == ABACUS_NF_SUM_FP32) {
+                            out[0] = totf[s][0] * F.scalef;
+                            out[1] = totf[s][1] * F.scalef;
+                            out[2] = totf[s][2] * F.scalef;
+                        } else {
+                            out[0] = (float)(tot[s][0] * F.scale);
+                            out[1] = (float)(tot[s][1] * F.scale);
+                            out[2] = (float)(tot[s][2] * F.scale);
+                        }
+                    } else {
+                        double *out = a.partials + 3 * (pb + idx);
+                        if constexpr (MODE == ABACUS_NF_SUM_FP32) {
+                            out[0] = totf[s][0];
+                            out[1] = totf[s][1];
+                            out[2] = totf[s][2];
+                        } else {
+                            out[0] = tot[s][0];
+                            out[1] = tot[s][1];
+                            out[2] = tot[s][2];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Sinks whose source list was split: add the parts in order and write the result.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ ws, int64_t partial_capacity,
+                                                  const int32_t *__restrict__ keys, const int32_t *__restrict__ cs,
+                                                  const int32_t *__restrict__ perm,
+                                                  const int32_t *__restrict__ cell_parts,
+                                                  const int64_t *__restrict__ cell_pbase,
+                                                  const double *__restrict__ partials,
+                                                  const BoxDev *__restrict__ boxes, int n_boxes,
+                                                  const ForceBox *__restrict__ fbox, float *__restrict__ acc,
+                                                  int64_t n) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n || ws->overflow) return;
+    const int32_t c = keys[s];
+    const int P = cell_parts[c];
+    if (P <= 1) return;
+    const int cs0 = cs[c], nc = cs[c + 1] - cs0;
+    const int64_t base = cell_pbase[c] + (s - cs0);
+    if (base + (int64_t)(P - 1) * nc >= partial_capacity) return;
+    const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, c) : 0;
+    const ForceBox F = fbox[b];
+    float *out = acc + 3 * (int64_t)perm[s];
+    for (int d = 0; d < 3; d++) {
+        if constexpr (MODE == ABACUS_NF_SUM_FP32) {
+            float t = 0.f;
+            for (int p = 0; p < P; p++) t += (float)partials[3 * (base + (int64_t)p * nc) + d];
+            out[d] = t * F.scalef;
+        } else {
+            double t = 0.0;
+            for (int p = 0; p < P; p++) t += partials[3 * (base + (int64_t)p * nc) + d];
+            out[d] = (float)(t * F.scale);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- variant dispatch
+
+typedef void (*ForcesKernel)(KArgs);
+
+template <int KIND, int MODE, int S>
+ForcesKernel pick_u(int U) {
+    switch (U) {
+        case 1: return k_forces<KIND, MODE, S, 1>;
+        case 4: return k_forces<KIND, MODE, S, 4>;
+        default: return k_forces<KIND, MODE, S, 2>;
+    }
+}
+
+template <int KIND, int MODE>
+ForcesKernel pick_s(int S, int U) {
+    switch (S) {
+        case 1: return pick_u<KIND, MODE, 1>(U);
+        case 4: return pick_u<KIND, MODE, 4>(U);
+        default: return pick_u<KIND, MODE, 2>(U);
+    }
+}
+
+template <int KIND>
+ForcesKernel pick_mode(int mode, int S, int U) {
+    switch (mode) {
+        case ABACUS_NF_SUM_COMP32: return pick_s<KIND, ABACUS_NF_SUM_COMP32>(S, U);
+        case ABACUS_NF_SUM_FP64: return pick_s<KIND, ABACUS_NF_SUM_FP64>(S, U);
+        default: return pick_s<KIND, ABACUS_NF_SUM_FP32>(S, U);
+    }
+}
+
+ForcesKernel pick_kernel(abacus_nf_kind kind, abacus_nf_sum mode, int S, int U) {
+    return kind == ABACUS_NF_PLUMMER ? pick_mode<ABACUS_NF_PLUMMER>(mode, S, U)
+                                     : pick_mode<ABACUS_NF_SPLINE>(mode, S, U);
+}
+
+size_t region_bytes(const abacus_nf_tuning &t) {
+    size_t stage = (size_t)t.chunk * sizeof(float4);
+    size_t red = (size_t)64 * t.sinks_per_lane * sizeof(double);
+    size_t main = stage > red ? stage : red;
+    return (main + (size_t)2 * 49 * sizeof(Seg) + 15) & ~(size_t)15;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+hipError_t launch_set_force_boxes(const double *eps, const double *gm, const abacus_nf_box *boxes, int n_boxes,
+                                  ForceBox *dst, hipStream_t st) {
+    for (int first = 0; first < n_boxes; first += kFBoxChunk) {
+        FBoxChunk ch;
+        memset(&ch, 0, sizeof(ch));
+        ch.first = first;
+        ch.count = n_boxes - first < kFBoxChunk ? n_boxes - first : kFBoxChunk;
+        for (int k = 0; k < ch.count; k++) {
+            const int b = first + k;
+            const double w = boxes[b].box / boxes[b].K;
+            const double e = eps[b] / w;
+            ForceBox &f = ch.f[k];
+            f.c0 = (float)(10.0 / (e * e * e));
+            f.c1 = (float)(-15.0 / (e * e * e * e));
+            f.c2 = (float)(6.0 / (e * e * e * e * e));
+            f.eps2 = (float)(e * e);
+            f.scale = gm[b] / (w * w);
+            f.scalef = (float)f.scale;
+            f.pad = 0;
+        }
+        hipLaunchKernelGGL(k_set_fbox, dim3(1), dim3(kFBoxChunk), 0, st, ch, dst);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_count_interactions(const ForcesArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_wl_clear, dim3(1), dim3(kNumClasses), 0, st, a.ws, a.tune.part_sources);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.n_cells <= 0) return e;
+    hipLaunchKernelGGL(k_wl_cells, dim3(grid_for(a.n_cells, 256)), dim3(256), 0, st, a.cell_start, a.boxes,
+                       a.n_boxes, a.n_cells, a.R, a.tune.sinks_per_lane, a.tune.max_lanes, a.cell_nsrc, a.ws);
+    return hipGetLastError();
+}
+
+hipError_t build_work_list(const ForcesArgs &a, hipStream_t st) {
+    hipError_t e = launch_count_interactions(a, st);
+    if (e != hipSuccess || a.n_cells <= 0) return e;
+    const int S = a.tune.sinks_per_lane, ML = a.tune.max_lanes;
+    const unsigned gc = grid_for(a.n_cells, 256);
+    hipLaunchKernelGGL(k_wl_plan, dim3(1), dim3(64), 0, st, a.ws, a.partial_capacity, a.item_capacity, a.n_total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wl_count, dim3(gc), dim3(256), 0, st, a.cell_start, a.cell_nsrc, a.n_cells, S, ML, a.ws,
+                       a.cell_parts, a.cell_pdem);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = scan_i64_add_exclusive(a.cell_pdem, a.cell_pbase, a.n_cells, a.scan_temp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wl_classes, dim3(1), dim3(64), 0, st, a.ws, a.item_capacity, a.cell_pbase, a.cell_pdem,
+                       a.n_cells, a.partial_capacity, a.err);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wl_emit, dim3(gc), dim3(256), 0, st, a.cell_start, a.cell_nsrc, a.cell_parts, a.boxes,
+                       a.n_boxes, a.n_cells, S, ML, a.ws, a.items, a.item_capacity);
+    return hipGetLastError();
+}
+
+int forces_grid(const abacus_nf_tuning &t, abacus_nf_kind kind, abacus_nf_sum mode, int device) {
+    ForcesKernel kfn = pick_kernel(kind, mode, t.sinks_per_lane, t.unroll);
+    const size_t lds = region_bytes(t) * kWaves;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kfn, kThreads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    if (t.waves_per_cu > 0) {
+        int want = (t.waves_per_cu + kWaves - 1) / kWaves;
+        if (want < per_cu) per_cu = want;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+    return per_cu * cus;
+}
+
+hipError_t launch_forces(const ForcesArgs &a, hipStream_t st) {
+    if (a.n_total <= 0) return hipSuccess;
+    KArgs k;
+    k.spos = a.spos;
+    k.cs = a.cell_start;
+    k.perm = a.perm;
+    k.items = a.items;
+    k.ws = a.ws;
+    k.boxes = a.boxes;
+    k.fbox = a.fbox;
+    k.cell_parts = a.cell_parts;
+    k.cell_pbase = a.cell_pbase;
+    k.partials = a.partials;
+    k.acc = a.acc;
+    k.R = a.R;
+    k.chunk = a.tune.chunk;
+    k.max_lanes = a.tune.max_lanes;
+    k.region = (int)region_bytes(a.tune);
+    ForcesKernel kfn = pick_kernel(a.kind, a.mode, a.tune.sinks_per_lane, a.tune.unroll);
+    hipLaunchKernelGGL(kfn, dim3(a.grid), dim3(kThreads), (size_t)k.region * kWaves, st, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const ForcesArgs &a, hipStream_t st) {
+    if (a.n_total <= 0) return hipSuccess;
+    const unsigned gn = grid_for(a.n_total, 256);
+    if (a.mode == ABACUS_NF_SUM_FP32)
+        hipLaunchKernelGGL(k_finalize<ABACUS_NF_SUM_FP32>, dim3(gn), dim3(256), 0, st, a.ws, a.partial_capacity,
+                           a.keys, a.cell_start, a.perm,
+                           a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.n_total);
+    else
+        hipLaunchKernelGGL(k_finalize<ABACUS_NF_SUM_FP64>, dim3(gn), dim3(256), 0, st, a.ws, a.partial_capacity,
+                           a.keys, a.cell_start, a.perm,
+                           a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.n_total);
+    return hipGetLastError();
+}
+
+}  // namespace anf

@@ -1,0 +1,152 @@
+// Internal declarations shared by the HIP translation units of libabacus_nf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/abacus_nf.h"
+
+namespace anf {
+
+// One periodic box, resident on the device for the binning and the work list.
+struct BoxDev {
+    int64_t offset;     // first particle of the box in the input array
+    int64_t n;          // particles in the box
+    double L;           // side
+    double s;           // K / L, computed once on the host in FP64
+    int32_t K;          // cells per side
+    int32_t cell_base;  // global index of the box's first cell
+};
+
+// Per-box constants of one forces call, in cell-width units.
+struct ForceBox {
+    float c0, c1, c2;   // spline: g = min(rinv^3, c0 + r2 * (c1 * rinv + c2))
+    float eps2;         // Plummer: g = (r2 + eps2)^(-3/2)
+    double scale;       // G*m / w^2: converts a cell-unit sum into an acceleration
+    float scalef;       // the same in FP32 (plain FP32 mode)
+    int32_t pad;
+};
+
+// One unit of work of the persistent force kernel: a tile of sinks of one
+// cell against one part of that cell's near-field source list.
+struct Item {
+    int32_t cell, tile, part, box;
+};
+
+constexpr int kNumClasses = 64;
+
+// Device-side state of the work list of one forces call.
+struct WorkState {
+    unsigned long long interactions;  // sum over cells of n_c * sources(c)
+    unsigned long long part_demand;   // partial slots needed at the base part size
+    int32_t n_items;                  // items emitted (clamped to the capacity)
+    int32_t cursor;                   // next item for the persistent kernel
+    int32_t part_iters;               // effective part length (source iterations per lane)
+    int32_t overflow;                 // non-zero when a list outgrew its capacity
+    unsigned long long base_items;    // items with every source list unsplit
+    unsigned long long split_items;   // items of cells whose source list is split
+    int32_t class_count[kNumClasses];
+    int32_t class_fill[kNumClasses];
+    int32_t class_base[kNumClasses];
+};
+
+// Tile geometry of a cell with n sinks: L lanes share each sink group, G
+// groups per wave, S sinks per lane, so one tile holds cap = G * S sinks.
+struct TileGeom {
+    int L, G, cap;
+};
+
+__host__ __device__ inline TileGeom tile_geom(int n, int S, int max_lanes) {
+    TileGeom t;
+    int groups = (n + S - 1) / S;
+    if (groups >= 64 || n <= 0) {
+        t.L = 1;
+    } else {
+        int L = 64 / groups;
+        t.L = L < max_lanes ? L : max_lanes;
+    }
+    t.G = 64 / t.L;
+    t.cap = t.G * S;
+    return t;
+}
+
+// Box of particle i: the last box whose offset is <= i (boxes partition the input in order).
+__device__ inline int box_of_particle(const BoxDev *boxes, int n_boxes, int64_t i) {
+    int lo = 0, hi = n_boxes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].offset <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Box of global cell c: the last box whose cell_base is <= c.
+__device__ inline int box_of_cell(const BoxDev *boxes, int n_boxes, int32_t c) {
+    int lo = 0, hi = n_boxes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].cell_base <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Error reporting: the first device error since the last abacus_nf_sync.
+int *device_error_word(int device);   // host accessor (allocates on first use)
+
+// Launch helpers (cells.hip)
+hipError_t launch_set_boxes(const abacus_nf_box *boxes, int n_boxes, const int32_t *cell_base,
+                            BoxDev *dst, hipStream_t st);
+hipError_t launch_bin(const float *pos, int64_t n, const BoxDev *boxes, int n_boxes, int32_t *keys,
+                      int32_t *vals, int *err, hipStream_t st);
+size_t radix_temp_bytes(int64_t n);
+hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_tmp, int32_t *vals_tmp,
+                            void *temp, int64_t n, int key_bits, hipStream_t st, int32_t **keys_out,
+                            int32_t **vals_out);
+size_t scan_temp_bytes(int64_t n);
+hipError_t scan_i32_max_inclusive(const int32_t *in, int32_t *out, int64_t n, void *temp, hipStream_t st);
+hipError_t scan_i64_add_exclusive(const int64_t *in, int64_t *out, int64_t n, void *temp, hipStream_t st);
+hipError_t launch_cell_start(const int32_t *keys_sorted, int64_t n, int64_t n_cells, int32_t *endpos,
+                             int32_t *cell_start, void *scan_temp, hipStream_t st);
+hipError_t launch_gather(const float *pos, const int32_t *perm, const int32_t *keys_sorted, int64_t n,
+                         const BoxDev *boxes, int n_boxes, float4 *spos, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+
+// Work list and forces (forces.hip)
+struct ForcesArgs {
+    const float4 *spos;
+    const int32_t *cell_start;
+    const int32_t *perm;
+    const int32_t *keys;
+    const BoxDev *boxes;
+    const ForceBox *fbox;
+    int n_boxes;
+    int64_t n_total;
+    int64_t n_cells;
+    int R;
+    Item *items;
+    int64_t item_capacity;
+    WorkState *ws;
+    int32_t *cell_nsrc;
+    int32_t *cell_parts;
+    int64_t *cell_pdem;
+    int64_t *cell_pbase;
+    double *partials;
+    int64_t partial_capacity;
+    float *acc;
+    int *err;
+    abacus_nf_kind kind;
+    abacus_nf_sum mode;
+    abacus_nf_tuning tune;
+    int grid;        // persistent-kernel workgroups
+    void *scan_temp;
+};
+
+hipError_t launch_set_force_boxes(const double *eps, const double *gm, const abacus_nf_box *boxes, int n_boxes,
+                                  ForceBox *dst, hipStream_t st);
+hipError_t build_work_list(const ForcesArgs &a, hipStream_t st);
+hipError_t launch_forces(const ForcesArgs &a, hipStream_t st);
+hipError_t launch_finalize(const ForcesArgs &a, hipStream_t st);
+int forces_grid(const abacus_nf_tuning &t, abacus_nf_kind kind, abacus_nf_sum mode, int device);
+hipError_t launch_count_interactions(const ForcesArgs &a, hipStream_t st);
+
+}  // namespace anf

@@ -1,0 +1,375 @@
+"""Parity of the HIP near-field path with the FP64 oracle (needs an MI355X).
+
+Every call goes through the C ABI (paper_2110_11398_amd's ctypes binding).
+Tolerances:
+  * cell structures (cell of each particle, order within a cell, offsets) are
+    integer results and must match bit for bit; the cell-relative FP32
+    coordinates must equal the FP64 value t - (c + 1/2) rounded once;
+  * accelerations: median fractional error <= 1e-5 against the FP64 oracle
+    (the target stated for the method), 99th percentile <= 1e-4, and for every
+    sink |a - a_ref| <= 1e-3 |a_ref| + 1e-5 S_i, where S_i = G*m sum_j |d_j| g_j
+    is the sum of the magnitudes of its pair terms.  The derivation of these
+    bounds from the FP32 arithmetic is in the design notes (cell-relative
+    coordinates are exact to 2^-25 cell widths; each pair term carries a few
+    units of FP32 rounding; the largest terms dominate the error).
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import SPLINE, PLUMMER  # noqa: E402
+from workloads import gen  # noqa: E402
+
+MED_TOL, P99_TOL = 1e-5, 1e-4
+
+
+@pytest.fixture(scope="module")
+def nf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_11398_amd as m
+    m.library()
+    return m
+
+
+def run(nf, pos_np, boxes, eps, gm, kind=SPLINE, mode=1, R=2, tuning=None, cells=None):
+    pos = torch.from_numpy(np.ascontiguousarray(pos_np, dtype=np.float32)).cuda()
+    c = nf.build_cells(pos, boxes, R, cells=cells)
+    if tuning:
+        c.set_tuning(**tuning)
+    acc = c.forces(eps, gm, kind, mode)
+    nf.sync()
+    return acc.cpu().numpy().astype(np.float64), c
+
+
+def check(a, ref, mag, what=""):
+    na = np.linalg.norm(ref, axis=1)
+    err = np.linalg.norm(a - ref, axis=1)
+    nz = na > 0
+    fe = err[nz] / na[nz]
+    med = float(np.median(fe)) if fe.size else 0.0
+    p99 = float(np.percentile(fe, 99)) if fe.size else 0.0
+    bound = 1e-3 * na + 1e-5 * mag + 1e-30
+    worst = float(np.max(err / bound)) if err.size else 0.0
+    print(f"{what}: n={a.shape[0]} median={med:.3e} p99={p99:.3e} worst/bound={worst:.3f}", flush=True)
+    assert np.all(np.isfinite(a)), what
+    assert med <= MED_TOL, (what, med)
+    assert p99 <= P99_TOL, (what, p99)
+    assert worst <= 1.0, (what, worst)
+    return med, p99
+
+
+# ---------------------------------------------------------------- cell structure
+
+def expected_cells(pos, boxes):
+    """Cell keys (global), stable order, offsets and cell-relative coordinates, from the oracle's cell rule."""
+    keys, rel = [], []
+    base, off = 0, 0
+    for n, L, K in boxes:
+        p = pos[off:off + n]
+        keys.append(oracle.bin_cells(p, L, K).astype(np.int64) + base)
+        x = p.astype(np.float64)
+        t = (x - L * np.floor(x / L)) * (K / L)
+        c = np.minimum(np.floor(t), K - 1)
+        r = np.empty((n, 4), np.float32)
+        r[:, :3] = (t - (c + 0.5)).astype(np.float32)
+        r[:, 3] = c[:, 2].astype(np.float32)
+        rel.append(r)
+        base += K ** 3
+        off += n
+    keys = np.concatenate(keys) if keys else np.zeros(0, np.int64)
+    rel = np.concatenate(rel) if rel else np.zeros((0, 4), np.float32)
+    perm = np.argsort(keys, kind="stable")
+    start = np.concatenate([[0], np.cumsum(np.bincount(keys, minlength=base))]).astype(np.int32)
+    return perm.astype(np.int32), start, rel[perm], keys[perm].astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["tiny", "ragged", "faces", "multibox", "one_cell", "sparse", "wrapped"])
+def test_build_cells_is_exact(nf, case):
+    rng = np.random.default_rng(zlib.crc32(case.encode()))
+    if case == "tiny":
+        w = gen.workload("tiny")
+        pos, boxes = w.boxes[0].pos, [(w.boxes[0].n, 1.0, 8)]
+    elif case == "ragged":
+        pos = rng.random((1_000_003, 3)).astype(np.float32)
+        boxes = [(len(pos), 1.0, 37)]
+    elif case == "faces":
+        K = 16
+        q = rng.integers(0, K, size=(20000, 3)) / K
+        pos = q.astype(np.float32)
+        pos[:100] = np.nextafter(np.float32(1), np.float32(0))
+        boxes = [(len(pos), 1.0, K)]
+    elif case == "multibox":
+        sizes = [3000, 1, 0, 70000, 4097]
+        Ks = [5, 7, 9, 40, 6]
+        Ls = [1.0, 2.5, 1.0, 3.0, 0.5]
+        pos = np.concatenate([rng.random((n, 3)) * L for n, L in zip(sizes, Ls)]).astype(np.float32)
+        boxes = list(zip(sizes, Ls, Ks))
+    elif case == "one_cell":
+        pos = (0.5 + 0.01 * rng.random((50000, 3))).astype(np.float32)
+        boxes = [(len(pos), 1.0, 5)]
+    elif case == "sparse":
+        pos = rng.random((3000, 3)).astype(np.float32)
+        boxes = [(len(pos), 1.0, 200)]
+    else:  # positions outside [0, L) are wrapped by the cell rule
+        pos = (rng.random((30000, 3)) * 3.0 - 1.0).astype(np.float32)
+        boxes = [(len(pos), 1.0, 11)]
+    posd = torch.from_numpy(pos).cuda()
+    c = nf.build_cells(posd, boxes, 2)
+    nf.sync()
+    perm, start, spos, keys = expected_cells(pos, boxes)
+    assert np.array_equal(c.copy(nf.abacus_nf.ARRAY_PERM).cpu().numpy(), perm)
+    assert np.array_equal(c.copy(nf.abacus_nf.ARRAY_CELL_START).cpu().numpy(), start)
+    assert np.array_equal(c.copy(nf.abacus_nf.ARRAY_CELL_KEY).cpu().numpy(), keys)
+    got = c.copy(nf.abacus_nf.ARRAY_SPOS).cpu().numpy()
+    assert np.array_equal(got, spos)
+    c.free()
+
+
+# ---------------------------------------------------------------- forces vs oracle
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = gen.workload("tiny")
+    b = w.boxes[0]
+    ref = {}
+    for kind in (SPLINE, PLUMMER):
+        ref[kind] = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, return_mag=True, return_pairs=True)
+    return b, ref
+
+
+@pytest.mark.parametrize("kind", [SPLINE, PLUMMER])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_tiny_all_sinks(nf, tiny, kind, mode):
+    b, ref = tiny
+    a, c = run(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], kind, mode)
+    acc, pairs, mag = ref[kind]
+    check(a, acc, mag, f"tiny kind={kind} mode={mode}")
+    assert c.interactions() == pairs
+    c.free()
+
+
+def test_modes_order_of_accuracy(nf, tiny):
+    """Compensated and FP64 accumulation are at least as close to the oracle as plain FP32 (median)."""
+    b, ref = tiny
+    acc = ref[SPLINE][0]
+    meds = []
+    for mode in (0, 1, 2):
+        a, c = run(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], SPLINE, mode)
+        fe = np.linalg.norm(a - acc, axis=1) / np.linalg.norm(acc, axis=1)
+        meds.append(np.median(fe))
+        c.free()
+    print("median frac err by mode", meds, flush=True)
+    assert meds[1] <= meds[0] * 1.05 and meds[2] <= meds[0] * 1.05
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(sinks_per_lane=1, unroll=1, chunk=64),
+    dict(sinks_per_lane=1, unroll=4, chunk=512),
+    dict(sinks_per_lane=4, unroll=2, chunk=512),
+    dict(sinks_per_lane=4, unroll=4, chunk=256, max_lanes=1),
+    dict(sinks_per_lane=2, unroll=2, chunk=128, max_lanes=3),
+    dict(sinks_per_lane=2, unroll=1, part_sources=1024),
+])
+def test_tiling_variants(nf, tiny, tuning):
+    b, ref = tiny
+    for mode in (0, 1):
+        a, c = run(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], SPLINE, mode, tuning=tuning)
+        check(a, ref[SPLINE][0], ref[SPLINE][2], f"tiling {tuning} mode={mode}")
+        c.free()
+
+
+def _edge_case(case, rng):
+    """(positions, [(n, L, K)], eps list, R)"""
+    if case == "single":
+        return np.array([[0.3, 0.4, 0.5]], np.float32), [(1, 1.0, 5)], [0.01], 2
+    if case == "pair_across_boundary":
+        return np.array([[0.001, 0.5, 0.5], [0.999, 0.5, 0.5]], np.float32), [(2, 1.0, 5)], [0.001], 2
+    if case == "coincident":
+        p = rng.random((3000, 3)).astype(np.float32)
+        p[1000:2000] = p[:1000]
+        p[2000:2010] = p[0]
+        return p, [(3000, 1.0, 6)], [0.02], 2
+    if case == "one_heavy_cell":
+        p = (0.41 + 0.02 * rng.random((20000, 3))).astype(np.float32)
+        return p, [(20000, 1.0, 5)], [0.004], 2
+    if case == "halo_plus_background":
+        p = np.concatenate([rng.random((20000, 3)), 0.5 + 0.003 * rng.standard_normal((20000, 3))]) % 1.0
+        return p.astype(np.float32), [(40000, 1.0, 10)], [0.0005], 2
+    if case == "sparse":
+        return rng.random((4000, 3)).astype(np.float32), [(4000, 1.0, 40)], [0.002], 2
+    if case == "K5_all_wrap":
+        return rng.random((5000, 3)).astype(np.float32), [(5000, 1.0, 5)], [0.01], 2
+    if case == "R1":
+        return rng.random((20000, 3)).astype(np.float32), [(20000, 1.0, 9)], [0.005], 1
+    if case == "R3":
+        return rng.random((20000, 3)).astype(np.float32), [(20000, 1.0, 9)], [0.005], 3
+    if case == "box_side_2_5":
+        return (rng.random((15000, 3)) * 2.5).astype(np.float32), [(15000, 2.5, 12)], [0.01], 2
+    if case == "faces":
+        K = 8
+        p = (rng.integers(0, 4 * K, size=(6000, 3)) / (4 * K)).astype(np.float32)
+        return p, [(6000, 1.0, K)], [0.003], 2
+    raise KeyError(case)
+
+
+EDGE = ["single", "pair_across_boundary", "coincident", "one_heavy_cell", "halo_plus_background", "sparse",
+        "K5_all_wrap", "R1", "R3", "box_side_2_5", "faces"]
+
+
+@pytest.mark.parametrize("case", EDGE)
+@pytest.mark.parametrize("kind", [SPLINE, PLUMMER])
+def test_edge_cases(nf, case, kind):
+    rng = np.random.default_rng(zlib.crc32(case.encode()))
+    p, boxes, eps, R = _edge_case(case, rng)
+    n, L, K = boxes[0]
+    gm = [1.0 / n]
+    ref, pairs, mag = oracle.forces(p, L, K, R, eps[0], kind, gm[0], return_pairs=True, return_mag=True)
+    for mode in (0, 1):
+        a, c = run(nf, p, boxes, eps, gm, kind, mode, R=R)
+        assert c.interactions() == pairs
+        if case == "single":
+            assert np.all(a == 0.0)
+        else:
+            check(a, ref, mag, f"{case} kind={kind} mode={mode}")
+        c.free()
+
+
+def test_forced_source_splitting_matches(nf):
+    """A heavy cell with its source list split into many parts (deterministic FP64 combination)."""
+    rng = np.random.default_rng(7)
+    p = np.concatenate([rng.random((5000, 3)), 0.3 + 0.02 * rng.random((30000, 3))]).astype(np.float32)
+    boxes, eps = [(len(p), 1.0, 6)], [0.002]
+    ref, mag = oracle.forces(p, 1.0, 6, 2, eps[0], SPLINE, 1.0 / len(p), return_mag=True)
+    for mode in (0, 1, 2):
+        a, c = run(nf, p, boxes, eps, [1.0 / len(p)], SPLINE, mode, tuning=dict(part_sources=1024))
+        check(a, ref, mag, f"split mode={mode}")
+        c.free()
+
+
+def test_empty_input(nf):
+    p = np.zeros((0, 3), np.float32)
+    a, c = run(nf, p, [(0, 1.0, 5)], [0.01], [1.0])
+    assert a.shape == (0, 3)
+    assert c.interactions() == 0
+    c.free()
+
+
+def test_batched_boxes_equal_single_boxes(nf):
+    """Independent boxes in one batch give bit-identical results to each box alone."""
+    w = gen.workload("batched", n_boxes=6, lo=20 ** 3, hi=40 ** 3)
+    pos = w.concat_positions()
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    eps = [b.eps for b in w.boxes]
+    gm = [b.gm for b in w.boxes]
+    a, c = run(nf, pos, boxes, eps, gm, SPLINE, 1)
+    c.free()
+    off = 0
+    for b in w.boxes:
+        s, cs = run(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], SPLINE, 1)
+        assert np.array_equal(a[off:off + b.n], s)
+        ref, mag = oracle.forces(b.pos, b.box, b.K, 2, b.eps, SPLINE, b.gm, return_mag=True)
+        check(s, ref, mag, f"batched box n={b.n} K={b.K}")
+        cs.free()
+        off += b.n
+
+
+def test_run_to_run_bit_identical(nf):
+    w = gen.workload("clustered", side=64, K=16, n_halos=64)
+    b = w.boxes[0]
+    r1, c1 = run(nf, b.pos, [(b.n, 1.0, b.K)], [b.eps], [b.gm], SPLINE, 1)
+    r2, c2 = run(nf, b.pos, [(b.n, 1.0, b.K)], [b.eps], [b.gm], SPLINE, 1, cells=c1)
+    assert np.array_equal(r1, r2)
+    c1.free()
+
+
+def test_permuted_input_gives_permuted_output(nf):
+    rng = np.random.default_rng(12)
+    p = rng.random((30000, 3)).astype(np.float32)
+    perm = rng.permutation(len(p))
+    a, c = run(nf, p, [(len(p), 1.0, 8)], [0.003], [1e-4], SPLINE, 2)
+    b, c2 = run(nf, p[perm], [(len(p), 1.0, 8)], [0.003], [1e-4], SPLINE, 2)
+    d = np.linalg.norm(b - a[perm], axis=1) / np.linalg.norm(a[perm], axis=1)
+    assert np.median(d) < 1e-6
+    c.free()
+    c2.free()
+
+
+# ---------------------------------------------------------------- clustered workloads at scale (sampled sinks)
+
+@pytest.fixture(scope="module")
+def clustered_full():
+    w = gen.workload("clustered")
+    return w.boxes[0]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_clustered_full_size_sampled(nf, clustered_full, mode):
+    """The bench workload (N=256^3, K=64, 4096 halos) at full size; 3000 sampled sinks vs the oracle."""
+    b = clustered_full
+    a, c = run(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], SPLINE, mode)
+    sinks = gen.sample_sinks(b.n, 3000, seed=99)
+    ref, mag = oracle.forces(b.pos, b.box, b.K, 2, b.eps, SPLINE, b.gm, sinks=sinks, return_mag=True)
+    check(a[sinks], ref, mag, f"clustered full mode={mode}")
+    c.free()
+
+
+def test_late_time_scaled_sampled(nf):
+    """The late-time recipe (8 per cell, half in halos with a = 0.05-0.5 cell) at 1/8 size."""
+    w = gen.workload("late", n=2 ** 24, K=128, n_halos=2048)
+    b = w.boxes[0]
+    sinks = gen.sample_sinks(b.n, 3000, seed=99)
+    for kind in (SPLINE, PLUMMER):
+        a, c = run(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], kind, 1)
+        ref, mag = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sinks, return_mag=True)
+        check(a[sinks], ref, mag, f"late scaled kind={kind}")
+        c.free()
+
+
+# ---------------------------------------------------------------- device-side errors
+
+def test_nonfinite_position_is_reported(nf):
+    p = np.random.default_rng(1).random((1000, 3)).astype(np.float32)
+    p[17, 1] = np.nan
+    pos = torch.from_numpy(p).cuda()
+    c = nf.build_cells(pos, [(1000, 1.0, 5)], 2)
+    c.forces([0.01], [1.0], SPLINE, 1)
+    with pytest.raises(nf.NearFieldError) as e:
+        nf.sync()
+    assert e.value.code == -5
+    nf.sync()  # the error word was cleared
+    c.free()
+
+
+def test_work_list_overflow_is_reported(nf):
+    p = np.random.default_rng(2).random((20000, 3)).astype(np.float32)
+    pos = torch.from_numpy(p).cuda()
+    c = nf.build_cells(pos, [(20000, 1.0, 10)], 2)
+    c.set_tuning(item_capacity=16)
+    c.forces([0.01], [1.0], SPLINE, 1)
+    with pytest.raises(nf.NearFieldError) as e:
+        nf.sync()
+    assert e.value.code == -4
+    c.reset_tuning()
+    acc = c.forces([0.01], [1.0], SPLINE, 1)
+    nf.sync()
+    assert torch.isfinite(acc).all()
+    c.free()
+
+
+def test_bad_tuning_is_rejected(nf):
+    p = torch.rand((100, 3), device="cuda")
+    c = nf.build_cells(p, [(100, 1.0, 5)], 2)
+    for bad in (dict(sinks_per_lane=3), dict(unroll=8), dict(chunk=100), dict(chunk=64, unroll=2), dict(chunk=1024),
+                dict(max_lanes=65), dict(part_sources=10)):
+        with pytest.raises(nf.NearFieldError):
+            c.set_tuning(**bad)
+    with pytest.raises(nf.NearFieldError):
+        c.forces([1e-9], [1.0])   # eps below 1e-5 cell widths
+    c.free()
