@@ -67,3 +67,19 @@ def brute_forces(pos32: np.ndarray, box: float, K: int, R: int, eps: float, kind
                 f = force_magnitude(r[nz], eps, kind) / r[nz]
                 acc[i] += (d[nz] * f[:, None]).sum(axis=0)
     return gm * acc, kept
+
+
+def brute_density(pos32: np.ndarray, box: float, K: int, R: int, b: float) -> np.ndarray:
+    """All-pairs x 27-image kernel density: sum of max(0, 1 - r^2/b^2) over the near field, self included."""
+    c, xt = cells_numpy(np.asarray(pos32, dtype=np.float32), box, K)
+    n = xt.shape[0]
+    rho = np.zeros(n)
+    shifts = np.array([(a, e, d) for a in (-1, 0, 1) for e in (-1, 0, 1) for d in (-1, 0, 1)], dtype=np.int64)
+    for i in range(n):
+        for s in shifts:
+            keep = np.all(np.abs(c + s * K - c[i]) <= R, axis=1)
+            if keep.any():
+                d = (xt[keep] + s * box) - xt[i]
+                w = 1.0 - (d * d).sum(axis=1) / (b * b)
+                rho[i] += w[w > 0].sum()
+    return rho

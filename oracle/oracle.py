@@ -58,7 +58,9 @@ class Oracle:
         lib.oracle_nf_kernel.argtypes = [vp, c_i64, c_d, ci, vp]
         lib.oracle_nf_forces.argtypes = [vp, c_i64, c_d, ci, ci, c_d, ci, c_d, vp, c_i64, ci, ci, vp, vp, vp]
         lib.oracle_nf_count_pairs.argtypes = [vp, c_i64, c_d, ci, ci, vp]
-        for f in (lib.oracle_nf_bin, lib.oracle_nf_kernel, lib.oracle_nf_forces, lib.oracle_nf_count_pairs):
+        lib.oracle_nf_density.argtypes = [vp, c_i64, c_d, ci, ci, c_d, vp, c_i64, ci, vp]
+        for f in (lib.oracle_nf_bin, lib.oracle_nf_kernel, lib.oracle_nf_forces, lib.oracle_nf_count_pairs,
+                  lib.oracle_nf_density):
             f.restype = ctypes.c_int
         self.lib = lib
         self.path = path
@@ -105,6 +107,21 @@ class Oracle:
             out.append(mag)
         return out[0] if len(out) == 1 else tuple(out)
 
+    def density(self, pos, box: float, K: int, R: int, b: float, sinks: Optional[np.ndarray] = None,
+                threads: int = 0) -> np.ndarray:
+        """Near-field kernel density sum max(0, 1 - r^2/b^2), self pair included (FP64)."""
+        p = _pos32(pos)
+        n = p.shape[0]
+        if sinks is None:
+            m, sp = n, None
+        else:
+            sk = np.ascontiguousarray(sinks, dtype=np.int64)
+            m, sp = sk.size, sk.ctypes.data
+        rho = np.zeros(m, dtype=np.float64)
+        _check(self.lib.oracle_nf_density(p.ctypes.data if n else None, n, float(box), int(K), int(R), float(b),
+                                          sp, m, int(threads), rho.ctypes.data if m else None), "density")
+        return rho
+
     def count_pairs(self, pos, box: float, K: int, R: int = 2) -> int:
         """Exact number of (sink, source) pairs, self pairs included, from cell occupancy."""
         p = _pos32(pos)
@@ -141,6 +158,10 @@ def forces(pos, box, K, R, eps, kind=SPLINE, gm=1.0, sinks=None, neumaier=False,
 
 def count_pairs(pos, box, K, R=2):
     return default().count_pairs(pos, box, K, R)
+
+
+def density(pos, box, K, R, b, sinks=None, threads=0):
+    return default().density(pos, box, K, R, b, sinks, threads)
 
 
 def forces_boxes(boxes: Sequence, R: int = 2, kind: int = SPLINE, threads: int = 0) -> np.ndarray:

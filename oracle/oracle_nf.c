@@ -34,7 +34,13 @@
  * multiply-add; build with -ffp-contract=off).  Linear cell index
  * (cx*K + cy)*K + cz.
  *
- * Coincident particles (including the self pair) contribute exactly zero.
+ * Kernel density estimate (Sec. 3.4 "Halo Finding"): computed in the same
+ * near-field pass, the density of particle i is the sum over its near field
+ * of the weight max(0, 1 - r^2/b^2) (b is a fixed radius; the paper takes 40%
+ * of the mean interparticle spacing).  The self pair is included (weight 1):
+ * the paper does not say, and this is the reading used here.
+ *
+ * Coincident particles (including the self pair) contribute exactly zero force.
  * Sums are plain FP64 in a fixed order (neighbour cells in lexicographic
  * (dx,dy,dz) order, sources in input order within a cell), or Neumaier
  * compensated FP64 when requested, as a self-check of the oracle's own
@@ -235,5 +241,80 @@ int oracle_nf_count_pairs(const float *pos, int64_t n, double L, int K, int R, i
     }
     *pairs = total;
     free(cnt); free(cell);
+    return ORACLE_OK;
+}
+
+/*
+ * Kernel density estimate over the near field (Sec. 3.4): for each sink,
+ * rho = sum over (j, image) in NF(i) of max(0, 1 - r^2/b^2), self pair included.
+ *   rho [nsinks] float64 out, in the order of `sinks` (all particles if NULL).
+ * b must be positive; pairs beyond R cells are not visited, so b should not
+ * exceed R cell widths for the estimate to see every neighbour within b.
+ */
+int oracle_nf_density(const float *pos, int64_t n, double L, int K, int R, double b, const int64_t *sinks,
+                      int64_t nsinks, int nthreads, double *rho) {
+    if (n < 0 || !(L > 0) || R < 1 || K < 2 * R + 1 || !(b > 0)) return ORACLE_EINVAL;
+    if (sinks == NULL) nsinks = n;
+    if (nsinks < 0 || (nsinks > 0 && (!rho || !pos))) return ORACLE_EINVAL;
+    if (nsinks == 0) return ORACLE_OK;
+    int64_t ncell = (int64_t)K * K * K;
+    double s = (double)K / L;
+    int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double *xt = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    int64_t *start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+    if (!cell || !xt || !start || !list || !fill) {
+        free(cell); free(xt); free(start); free(list); free(fill);
+        return ORACLE_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        int c3[3];
+        for (int d = 0; d < 3; d++) c3[d] = axis_cell((double)pos[3 * i + d], L, s, K, &xt[3 * i + d]);
+        cell[i] = (int32_t)(((int64_t)c3[0] * K + c3[1]) * K + c3[2]);
+    }
+    for (int64_t i = 0; i < n; i++) start[cell[i] + 1]++;
+    for (int64_t c = 0; c < ncell; c++) start[c + 1] += start[c];
+    memcpy(fill, start, sizeof(int64_t) * (size_t)ncell);
+    for (int64_t i = 0; i < n; i++) list[fill[cell[i]]++] = i;
+    const double b2 = b * b;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t q = 0; q < nsinks; q++) {
+        int64_t i = sinks ? sinks[q] : q;
+        if (i < 0 || i >= n) {
+            rho[q] = NAN;
+            continue;
+        }
+        int ci = cell[i];
+        int cz = ci % K, cy = (ci / K) % K, cx = ci / (K * K);
+        double xi = xt[3 * i], yi = xt[3 * i + 1], zi = xt[3 * i + 2];
+        double sum = 0.0;
+        for (int dx = -R; dx <= R; dx++) {
+            int ex = cx + dx, sx = 0;
+            if (ex < 0) { ex += K; sx = -1; } else if (ex >= K) { ex -= K; sx = 1; }
+            for (int dy = -R; dy <= R; dy++) {
+                int ey = cy + dy, sy = 0;
+                if (ey < 0) { ey += K; sy = -1; } else if (ey >= K) { ey -= K; sy = 1; }
+                for (int dz = -R; dz <= R; dz++) {
+                    int ez = cz + dz, sz = 0;
+                    if (ez < 0) { ez += K; sz = -1; } else if (ez >= K) { ez -= K; sz = 1; }
+                    int64_t cj = ((int64_t)ex * K + ey) * K + ez;
+                    for (int64_t k = start[cj]; k < start[cj + 1]; k++) {
+                        int64_t j = list[k];
+                        double ddx = (xt[3 * j] + sx * L) - xi;
+                        double ddy = (xt[3 * j + 1] + sy * L) - yi;
+                        double ddz = (xt[3 * j + 2] + sz * L) - zi;
+                        double w = 1.0 - (ddx * ddx + ddy * ddy + ddz * ddz) / b2;
+                        if (w > 0.0) sum += w;
+                    }
+                }
+            }
+        }
+        rho[q] = sum;
+    }
+    free(cell); free(xt); free(start); free(list); free(fill);
     return ORACLE_OK;
 }

@@ -22,6 +22,11 @@ MUTANTS = {
     "cutover_radius": ("if (r >= eps) return 1.0 / (r2 * r);", "if (r >= 0.9 * eps) return 1.0 / (r2 * r);"),
     "mass_applied_twice": ("acc[3 * q + 1] = gm * (a.s1 + a.c1);", "acc[3 * q + 1] = gm * gm * (a.s1 + a.c1);"),
     "neighbour_x_wrap": ("else if (ex >= K) { ex -= K; sx = 1; }", "else if (ex >= K) { ex -= K; sx = 0; }"),
+    "density_weight_power": ("double w = 1.0 - (ddx * ddx + ddy * ddy + ddz * ddz) / b2;",
+                             "double w = 1.0 - sqrt(ddx * ddx + ddy * ddy + ddz * ddz) / b;"),
+    "density_self_excluded": ("if (w > 0.0) sum += w;", "if (w > 0.0 && w < 1.0) sum += w;"),
+    "density_image_dropped": ("double ddz = (xt[3 * j + 2] + sz * L) - zi;\n                        double w",
+                              "double ddz = xt[3 * j + 2] - zi;\n                        double w"),
 }
 
 
@@ -50,14 +55,19 @@ def battery(o: oracle.Oracle) -> list:
     pts = np.array([[0.0, 0.125, 0.25], [0.124999993, 0.5, 0.875]], dtype=np.float32)
     if not np.array_equal(o.bin_cells(pts, 1.0, 8), [(0 * 8 + 1) * 8 + 2, (0 * 8 + 4) * 8 + 7]):
         bad.append("cell rule")
+    from oracle.brute import brute_density
+    pos = rng.random((300, 3)).astype(np.float32)
+    pos[:2] = [[0.5, 0.5, 0.001], [0.5, 0.5, 0.999]]
+    if not np.allclose(o.density(pos, 1.0, 5, 2, 0.12), brute_density(pos, 1.0, 5, 2, 0.12), rtol=1e-12, atol=0):
+        bad.append("density")
     return bad
 
 
 def _build_variant(tmp_path, name, old, new):
     src = open(oracle.SOURCE).read()
     if old is not None:
-        assert src.count(old) == 1, f"mutation anchor for {name} not unique"
-        src = src.replace(old, new)
+        assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+        src = src.replace(old, new, 1)   # the first occurrence: the force sum (the density follows it)
     path = os.path.join(tmp_path, f"oracle_{name}.c")
     open(path, "w").write(src)
     return oracle.Oracle(oracle.compile_oracle(path, os.path.join(tmp_path, f"liboracle_{name}.so")))

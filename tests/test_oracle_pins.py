@@ -253,3 +253,41 @@ def test_empty_and_invalid_arguments(orc):
         orc.forces(np.zeros((4, 3), np.float32), 1.0, 4, 2, 0.1)     # K < 2R+1
     with pytest.raises(ValueError):
         orc.forces(np.zeros((4, 3), np.float32), 1.0, 5, 2, 0.0)     # eps <= 0
+
+
+# ---------------------------------------------------------------- kernel density estimate (Sec. 3.4)
+
+@pytest.mark.parametrize("n,K", [(2, 5), (300, 5), (2000, 7)])
+def test_density_matches_brute_force(orc, n, K):
+    from oracle.brute import brute_density
+    rng = np.random.default_rng(n + K)
+    pos = rng.random((n, 3)).astype(np.float32)
+    pos[:2] = [[0.001, 0.5, 0.5], [0.999, 0.5, 0.5]]     # a pair across the periodic boundary
+    b = 0.6 / K
+    rho = orc.density(pos, 1.0, K, 2, b)
+    ref = brute_density(pos, 1.0, K, 2, b)
+    assert np.abs(rho - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_density_closed_forms(orc):
+    # isolated particles: only the self pair, weight 1
+    pos = np.array([[0.1, 0.1, 0.1], [0.6, 0.6, 0.6]], np.float32)
+    assert np.array_equal(orc.density(pos, 1.0, 5, 2, 0.05), [1.0, 1.0])
+    # a pair at distance r < b: 1 + (1 - r^2/b^2) each; r = b/2 -> 1.75
+    pos = np.array([[0.5, 0.5, 0.5], [0.5, 0.5, 0.5625]], np.float32)
+    np.testing.assert_allclose(orc.density(pos, 1.0, 5, 2, 0.125), [1.75, 1.75], rtol=1e-15)
+    # exactly at r = b the weight vanishes
+    np.testing.assert_allclose(orc.density(pos, 1.0, 5, 2, 0.0625), [1.0, 1.0], rtol=1e-15)
+
+
+def test_density_lattice(orc):
+    """Simple cubic lattice of spacing a: with a < b < sqrt(2) a each particle sees itself and its
+    6 face neighbours at distance a: rho = 1 + 6 (1 - a^2/b^2)."""
+    K, per = 6, 2
+    m = K * per
+    g = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"), -1).reshape(-1, 3)
+    a = 0.5                                   # dyadic spacing: the lattice is exact in FP32
+    pos = ((g + 0.5) * a).astype(np.float32)
+    b = 1.25 * a
+    rho = orc.density(pos, m * a, K, 2, b)
+    np.testing.assert_allclose(rho, 1 + 6 * (1 - 1 / 1.25 ** 2), rtol=1e-12)
