@@ -39,8 +39,9 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, kind: str, mode: str, launches: int):
-    """HBM bytes per force-kernel launch from a committed counter summary, if it matches these sources."""
+def traffic_from_profile(workload: str, kind: str, mode: str, tuning: dict):
+    """HBM bytes per force-kernel launch from a committed counter summary, if it was taken on these
+    kernel sources with this kernel variant (otherwise None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_forces_{workload}_{kind}_{mode}.json")
     if not os.path.exists(path):
         return None
@@ -50,34 +51,40 @@ def traffic_from_profile(workload: str, kind: str, mode: str, launches: int):
         return None
     if d.get("source_digest") != kernel_source_digest():
         return None
+    for k in ("sinks_per_lane", "unroll", "chunk", "occupancy", "max_lanes"):
+        if d.get("tuning", {}).get(k) != tuning.get(k):
+            return None
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(boxes, kind, target_s, threads, acc_gpu):
-    """Time the FP64 oracle on a bounded sample of sinks; also the GPU's error on that sample."""
+def oracle_sample(boxes, kind, target_s, threads, m_fixed=0):
+    """Time the FP64 oracle on a bounded sample of sinks of box 0 (about target_s seconds, or m_fixed sinks)."""
     import oracle
-    b = boxes[0]
     from workloads.gen import sample_sinks
-    m = 256
+    b = boxes[0]
+    m = m_fixed if m_fixed > 0 else 256
     t0 = time.perf_counter()
-    ref, pairs = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sample_sinks(b.n, m, 99),
-                               threads=threads, return_pairs=True)
+    sinks = sample_sinks(b.n, m, 99)
+    ref, pairs = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sinks, threads=threads,
+                               return_pairs=True)
     dt = time.perf_counter() - t0
-    if dt < target_s / 3:
+    if m_fixed <= 0 and dt < target_s / 3:
         m = int(min(b.n, max(m, m * target_s / max(dt, 1e-3))))
         t0 = time.perf_counter()
         sinks = sample_sinks(b.n, m, 99)
         ref, pairs = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sinks, threads=threads,
                                    return_pairs=True)
         dt = time.perf_counter() - t0
-    else:
-        sinks = sample_sinks(b.n, m, 99)
-    a = acc_gpu[sinks].astype(np.float64)
+    base = {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} sinks drawn without replacement (seed 99) of box 0; {pairs} FP64 pairs in {dt:.2f} s"}
+    return base, sinks, ref
+
+
+def frac_errors(acc_box0, sinks, ref):
+    a = acc_box0[sinks].astype(np.float64)
     na = np.linalg.norm(ref, axis=1)
     fe = np.linalg.norm(a - ref, axis=1)[na > 0] / na[na > 0]
-    return ({"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-             "sample": f"{m} sinks drawn without replacement (seed 99) of box 0; {pairs} FP64 pairs in {dt:.2f} s"},
-            float(np.median(fe)), float(np.percentile(fe, 99)), m)
+    return float(np.median(fe)), float(np.percentile(fe, 99))
 
 
 def main():
@@ -86,12 +93,22 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="clustered", choices=["tiny", "clustered", "precision", "batched", "late"])
-    ap.add_argument("--kind", default="spline", choices=list(KINDS))
-    ap.add_argument("--mode", default="fp32", choices=list(MODES))
+    ap.add_argument("--kind", default="spline", help="spline, plummer, or a comma list")
+    ap.add_argument("--mode", default="fp32", help="fp32, comp32, fp64, or a comma list")
+    ap.add_argument("--err-sinks", type=int, default=0,
+                    help="fixed size of the oracle sample (default: sized to about --cpu-seconds)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tune", action="store_true", help="autotune the force kernel before timing")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2110_11398_amd", "tuning_cache.json"),
+                    help="autotuner cache (JSON); the tuning for this device/kind/mode/size class is looked up "
+                         "there and searched (then recorded) if missing")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default tuning")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one step (build_cells + forces) in a HIP graph and time its replays")
     ap.add_argument("--tuning", default="", help="comma list k=v of abacus_nf_tuning fields")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (a known-size kernel that "
+                         "calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -103,7 +120,7 @@ def main():
     import paper_2110_11398_amd as nf
     from workloads import gen
 
-    kind, mode = KINDS[args.kind], MODES[args.mode]
+    gen.set_verbose(True)
     t0 = time.perf_counter()
     w = gen.workload(args.workload)
     log(f"generated {args.workload}: N={w.n_total} boxes={len(w.boxes)} in {time.perf_counter() - t0:.1f} s")
@@ -112,13 +129,39 @@ def main():
     eps = [b.eps for b in w.boxes]
     gm = [b.gm for b in w.boxes]
     acc = torch.empty((w.n_total, 3), dtype=torch.float32, device="cuda")
+    if args.copy_calibration_mb > 0:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
+    threads = min(16, os.cpu_count() or 1)
+    samples = {}
+    for kname in args.kind.split(","):
+        for mname in args.mode.split(","):
+            line = run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, KINDS[kname], MODES[mname], kname, mname)
+            if not args.no_cpu_baseline:
+                kind = KINDS[kname]
+                if kind not in samples:
+                    samples[kind] = oracle_sample(w.boxes, kind, args.cpu_seconds, threads, args.err_sinks)
+                base, sinks, ref = samples[kind]
+                line["cpu_baseline"] = base
+                med, p99 = frac_errors(acc[:w.boxes[0].n].cpu().numpy(), sinks, ref)
+                line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, len(sinks)
+            print(json.dumps(line), flush=True)
 
+
+def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mname):
     cells = nf.build_cells(pos, boxes, 2)
     if args.tuning:
         cells.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
-    if args.tune:
-        t = cells.autotune(eps, gm, kind, mode, acc, reps=2)
-        log(f"autotuned: {t.as_dict()}")
+    elif not args.no_tune:
+        t0 = time.perf_counter()
+        t = cells.autotune(eps, gm, kind, mode, acc, reps=2, cache_path=args.tune_cache)
+        log(f"tuning ({time.perf_counter() - t0:.1f} s): {t.as_dict()}")
     cells.forces(eps, gm, kind, mode, acc)
     nf.sync()
     interactions = cells.interactions()
@@ -129,53 +172,68 @@ def main():
         cells.forces(eps, gm, kind, mode, acc)
     nf.sync()
 
-    cells.set_timing(True)
+    graph = None
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            nf.build_cells(pos, boxes, 2, cells=cells)
+            cells.forces(eps, gm, kind, mode, acc)
+        graph.replay()
+        torch.cuda.synchronize()
+        nf.sync()
+    # HIP events around each stage, on the stream the kernels run on (eager steps); graph replays are
+    # timed as a whole and their stage split comes from the same steps run eagerly afterwards
+    cells.set_timing(graph is None)
     stage_ms = np.zeros(4)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.steps):
-        nf.build_cells(pos, boxes, 2, cells=cells)
-        cells.forces(eps, gm, kind, mode, acc)
-        stage_ms += np.array(cells.last_times())
+        if graph is not None:
+            graph.replay()
+        else:
+            nf.build_cells(pos, boxes, 2, cells=cells)
+            cells.forces(eps, gm, kind, mode, acc)
+            stage_ms += np.array(cells.last_times())
     e1.record()
     torch.cuda.synchronize()
     nf.sync()
-    cells.set_timing(False)
     ms_step = e0.elapsed_time(e1) / args.steps
     stage_ms /= args.steps
-    log(f"ms/step {ms_step:.3f}; stages ms build={stage_ms[0]:.3f} worklist={stage_ms[1]:.3f} "
-        f"kernel={stage_ms[2]:.3f} finalize={stage_ms[3]:.3f}")
+    if graph is not None:
+        cells.set_timing(True)
+        stage_ms = np.zeros(4)
+        for _ in range(args.steps):
+            nf.build_cells(pos, boxes, 2, cells=cells)
+            cells.forces(eps, gm, kind, mode, acc)
+            stage_ms += np.array(cells.last_times())
+        stage_ms /= args.steps
+        nf.sync()
+    cells.set_timing(False)
+    log(f"[{kname}/{mname}] ms/step {ms_step:.3f}; stages ms build={stage_ms[0]:.3f} "
+        f"worklist={stage_ms[1]:.3f} kernel={stage_ms[2]:.3f} finalize={stage_ms[3]:.3f}")
 
     step_s = ms_step / 1e3
     kern_s = stage_ms[2] / 1e3
+    tuning = cells.get_tuning().as_dict()
     achieved = FLOPS_PER_PAIR[kind] * interactions / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": traffic_from_profile(args.workload, args.kind, args.mode, 1),
+                "traffic": traffic_from_profile(args.workload, kname, mname, tuning),
                 "kernel": "k_forces", "kernel_ms": stage_ms[2],
                 "flops_per_launch": FLOPS_PER_PAIR[kind] * interactions}
-
     out = {"metric": METRIC, "value": interactions / step_s, "unit": "interactions/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {w.description}", "n": w.n_total, "boxes": len(w.boxes),
-                      "K": [b.K for b in w.boxes][:4], "kind": args.kind, "mode": args.mode,
-                      "interactions_per_step": interactions, "tuning": cells.get_tuning().as_dict()},
+                      "K": [b.K for b in w.boxes][:4], "kind": kname, "mode": mname,
+                      "interactions_per_step": interactions, "tuning": tuning, "hip_graph": bool(args.graph)},
            "particle_updates_per_s": w.n_total / step_s,
            "stages_ms": {"build_cells": stage_ms[0], "work_list": stage_ms[1], "forces_kernel": stage_ms[2],
                          "finalize": stage_ms[3]},
            "roofline": roofline}
-
-    if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        base, med, p99, m = cpu_baseline(w.boxes, kind, args.cpu_seconds, threads, acc[:w.boxes[0].n].cpu().numpy())
-        out["cpu_baseline"] = base
-        out["median_frac_err"] = med
-        out["p99_frac_err"] = p99
-        out["err_sample_sinks"] = m
     cells.free()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

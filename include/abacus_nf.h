@@ -131,6 +131,24 @@ int abacus_nf_forces(abacus_nf_cells cells, const double *eps, abacus_nf_kind ki
                      abacus_nf_sum mode, float *acc, void *hip_stream);
 
 /*
+ * abacus_nf_forces_density -- the same accelerations plus the kernel density
+ * estimate computed in the same near-field pass (Sec. 3.4 "Halo Finding":
+ * weight 1 - r^2/b^2 for pairs closer than b).  For every particle
+ *     rho_i = sum over its near field (self pair included) of max(0, 1 - r^2/b^2),
+ * a dimensionless count-weighted density (multiply by m / volume as needed).
+ *
+ *   b      host double [n_boxes]: kernel radius of each box in its length
+ *          unit (the paper uses 40% of the mean interparticle spacing).  Valid
+ *          range: 1e-4 <= b*K/L <= R, so every neighbour within b is in the
+ *          near field.
+ *   rho    device float32 [n_total], input order.
+ *   other arguments as for abacus_nf_forces; the density is summed like the
+ *   force (FP32, or FP32 chunks folded into FP64 for COMP32 and FP64 modes).
+ */
+int abacus_nf_forces_density(abacus_nf_cells cells, const double *eps, abacus_nf_kind kind, const double *gm,
+                             abacus_nf_sum mode, const double *b, float *acc, float *rho, void *hip_stream);
+
+/*
  * abacus_nf_sync -- wait for the stream, then return (and clear) the first
  * error recorded on the current device since the last sync: ENONFINITE,
  * ECAPACITY, or EDEVICE if the stream itself failed.
@@ -186,6 +204,9 @@ typedef struct {
     int32_t part_sources;    /* split a tile's source list into parts of about this many
                                 sources per lane (>= 1024)                                   */
     int32_t waves_per_cu;    /* persistent-kernel waves per compute unit (0 = occupancy)     */
+    int32_t occupancy;       /* register budget of the kernel variant: 0 = compiler's choice,
+                                6 or 8 = at least that many waves per SIMD                   */
+    int32_t reserved;        /* must be 0                                                    */
     int64_t item_capacity;   /* work-list capacity override (tests); 0 = sized from the batch */
 } abacus_nf_tuning;
 

@@ -12,7 +12,8 @@ import os
 from typing import Iterable, List, Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "libabacus_nf.so")
+# ABACUS_NF_LIBRARY selects another build of the same library (for comparing builds)
+_LIB_PATH = os.environ.get("ABACUS_NF_LIBRARY") or os.path.join(HERE, "libabacus_nf.so")
 
 SPLINE, PLUMMER = 0, 1
 SUM_FP32, SUM_COMP32, SUM_FP64 = 0, 1, 2
@@ -30,7 +31,7 @@ class Tuning(ctypes.Structure):
     """Mirror of abacus_nf_tuning (zero fields mean library default)."""
     _fields_ = [("sinks_per_lane", ctypes.c_int32), ("chunk", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("max_lanes", ctypes.c_int32), ("part_sources", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("item_capacity", ctypes.c_int64)]
+                ("occupancy", ctypes.c_int32), ("reserved", ctypes.c_int32), ("item_capacity", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -62,6 +63,8 @@ def library():
     sig = {
         "abacus_nf_build_cells": [vp, i64, ctypes.POINTER(BoxDesc), i32, i32, vp, ctypes.POINTER(vp)],
         "abacus_nf_forces": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int, vp, vp],
+        "abacus_nf_forces_density": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int,
+                                     ctypes.POINTER(d), vp, vp, vp],
         "abacus_nf_sync": [vp],
         "abacus_nf_free_cells": [vp],
         "abacus_nf_interactions": [vp, vp, ctypes.POINTER(i64)],
@@ -156,6 +159,25 @@ class Cells:
                                         ctypes.c_void_p(_stream_handle(stream)))
         _check(rc, "abacus_nf_forces")
         return out
+
+    def forces_density(self, eps: Sequence[float], gm: Sequence[float], b: Sequence[float], kind: int = SPLINE,
+                       mode: int = SUM_COMP32, out=None, rho=None, stream=None):
+        """abacus_nf_forces_density: accelerations [N,3] and kernel densities [N] (device tensors)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_total, 3), dtype=torch.float32, device="cuda")
+        if rho is None:
+            rho = torch.empty(self.n_total, dtype=torch.float32, device="cuda")
+        if not (out.is_cuda and out.dtype == torch.float32 and out.shape == (self.n_total, 3) and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float32 [N,3] GPU tensor")
+        if not (rho.is_cuda and rho.dtype == torch.float32 and rho.shape == (self.n_total,) and rho.is_contiguous()):
+            raise ValueError("rho must be a contiguous float32 [N] GPU tensor")
+        rc = library().abacus_nf_forces_density(self._h, _doubles(eps), int(kind), _doubles(gm), int(mode),
+                                                _doubles(b), ctypes.c_void_p(out.data_ptr() if out.numel() else None),
+                                                ctypes.c_void_p(rho.data_ptr() if rho.numel() else None),
+                                                ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_forces_density")
+        return out, rho
 
     def interactions(self, stream=None) -> int:
         v = ctypes.c_int64(0)

@@ -43,6 +43,10 @@ struct abacus_nf_cells_s {
     double *partials = nullptr;
     void *wscan_temp = nullptr;
 
+    // persistent-kernel grid of the last (kind, mode, tuning): queried once, outside any capture
+    int grid = 0;
+    int grid_key[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+
     // optional stage timing: event pairs for build, work list, kernel, finalize
     bool timing = false;
     hipEvent_t ev[8] = {nullptr};
@@ -150,6 +154,8 @@ bool resolve_tuning(const abacus_nf_tuning *in, abacus_nf_tuning *out) {
     if (t.max_lanes < 1 || t.max_lanes > 64) return false;
     if (t.part_sources < 1024) return false;
     if (t.waves_per_cu < 0 || t.waves_per_cu > 64) return false;
+    if (t.occupancy != 0 && t.occupancy != 6 && t.occupancy != 8) return false;
+    if (t.reserved != 0) return false;
     if (t.item_capacity < 0 || t.item_capacity >= INT32_MAX) return false;
     *out = t;
     return true;
@@ -318,7 +324,7 @@ static int ensure_work_buffers(abacus_nf_cells_s *h) {
     free_work_buffers(h);
     bool ok = dalloc(h->d_fbox, h->n_boxes) && dalloc(h->ws, 1) && dalloc(h->items, want_items) &&
               dalloc(h->cell_nsrc, nc) && dalloc(h->cell_parts, nc) && dalloc(h->cell_pdem, nc) &&
-              dalloc(h->cell_pbase, nc) && dalloc(h->partials, 3 * want_partials) &&
+              dalloc(h->cell_pbase, nc) && dalloc(h->partials, 4 * want_partials) &&
               dalloc_bytes(h->wscan_temp, scan_temp_bytes(nc));
     if (!ok) {
         free_work_buffers(h);
@@ -354,6 +360,7 @@ static ForcesArgs make_args(abacus_nf_cells_s *h, abacus_nf_kind kind, abacus_nf
     a.partials = h->partials;
     a.partial_capacity = h->wcap_partials;
     a.acc = acc;
+    a.rho = nullptr;
     a.err = err;
     a.kind = kind;
     a.mode = mode;
@@ -362,10 +369,17 @@ static ForcesArgs make_args(abacus_nf_cells_s *h, abacus_nf_kind kind, abacus_nf
     return a;
 }
 
-int abacus_nf_forces(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
-                     abacus_nf_sum mode, float *acc, void *hip_stream) {
+static int forces_impl(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                       abacus_nf_sum mode, const double *kde_b, float *acc, float *rho, void *hip_stream) {
     int rc = check_force_args(h, eps, kind, gm, mode, acc);
     if (rc != ABACUS_NF_OK) return rc;
+    if (kde_b) {
+        if (h->n_total > 0 && !rho) return ABACUS_NF_EINVAL;
+        for (int b = 0; b < h->n_boxes; b++) {
+            const double bc = kde_b[b] * h->boxes[b].K / h->boxes[b].box;
+            if (!std::isfinite(kde_b[b]) || !(bc >= 1e-4 && bc <= (double)h->R)) return ABACUS_NF_EINVAL;
+        }
+    }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
     if (dev != h->device) return ABACUS_NF_ESTATE;
@@ -375,9 +389,16 @@ int abacus_nf_forces(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, 
     hipStream_t st = (hipStream_t)hip_stream;
     if (h->n_total == 0) return ABACUS_NF_OK;
     ForcesArgs a = make_args(h, kind, mode, acc, err);
-    a.grid = forces_grid(h->tune, kind, mode, dev);
+    a.rho = kde_b ? rho : nullptr;
+    const int key[8] = {(int)kind, (int)mode, h->tune.sinks_per_lane, h->tune.unroll, h->tune.chunk,
+                        h->tune.waves_per_cu, dev * 2 + (kde_b ? 1 : 0), h->tune.occupancy};
+    if (memcmp(key, h->grid_key, sizeof(key)) != 0 || h->grid <= 0) {
+        h->grid = forces_grid(h->tune, kind, mode, kde_b != nullptr, dev);
+        memcpy(h->grid_key, key, sizeof(key));
+    }
+    a.grid = h->grid;
     mark(h, 1, false, st);
-    hipError_t e = launch_set_force_boxes(eps, gm, h->boxes.data(), h->n_boxes, h->d_fbox, st);
+    hipError_t e = launch_set_force_boxes(eps, gm, kde_b, kind, h->boxes.data(), h->n_boxes, h->d_fbox, st);
     if (e == hipSuccess) e = build_work_list(a, st);
     mark(h, 1, true, st);
     mark(h, 2, false, st);
@@ -388,6 +409,17 @@ int abacus_nf_forces(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, 
     mark(h, 3, true, st);
     if (e != hipSuccess) return hip_fail(e);
     return ABACUS_NF_OK;
+}
+
+int abacus_nf_forces(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                     abacus_nf_sum mode, float *acc, void *hip_stream) {
+    return forces_impl(h, eps, kind, gm, mode, nullptr, acc, nullptr, hip_stream);
+}
+
+int abacus_nf_forces_density(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                             abacus_nf_sum mode, const double *b, float *acc, float *rho, void *hip_stream) {
+    if (!b) return ABACUS_NF_EINVAL;
+    return forces_impl(h, eps, kind, gm, mode, b, acc, rho, hip_stream);
 }
 
 int abacus_nf_sync(void *hip_stream) {

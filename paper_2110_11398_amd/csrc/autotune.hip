@@ -32,7 +32,8 @@ std::string cache_key(abacus_nf_cells h, abacus_nf_kind kind, abacus_nf_sum mode
     return k.str();
 }
 
-// The cache file is a flat JSON object: {"key": [S, chunk, unroll, max_lanes, part_sources], ...}
+// The cache file is a flat JSON object:
+// {"key": [sinks_per_lane, chunk, unroll, max_lanes, part_sources, occupancy], ...}
 std::map<std::string, std::vector<long long>> read_cache(const char *path) {
     std::map<std::string, std::vector<long long>> m;
     std::ifstream f(path);
@@ -87,13 +88,14 @@ extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_n
     if (cache_path) {
         auto m = read_cache(cache_path);
         auto it = m.find(key);
-        if (it != m.end() && it->second.size() == 5) {
+        if (it != m.end() && it->second.size() == 6) {
             abacus_nf_tuning t = cur;
             t.sinks_per_lane = (int32_t)it->second[0];
             t.chunk = (int32_t)it->second[1];
             t.unroll = (int32_t)it->second[2];
             t.max_lanes = (int32_t)it->second[3];
             t.part_sources = (int32_t)it->second[4];
+            t.occupancy = (int32_t)it->second[5];
             if (abacus_nf_set_tuning(h, &t) == ABACUS_NF_OK) {
                 rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
                 if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
@@ -102,40 +104,56 @@ extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_n
             }
         }
     }
-    std::vector<abacus_nf_tuning> cand;
-    for (int S : {1, 2, 4})
-        for (int U : {1, 2, 4})
-            for (int chunk : {256, 512})
-                for (int ml : {8, 64}) {
-                    abacus_nf_tuning t = cur;
-                    t.sinks_per_lane = S;
-                    t.unroll = U;
-                    t.chunk = chunk;
-                    t.max_lanes = ml;
-                    cand.push_back(t);
-                }
     hipStream_t st = (hipStream_t)hip_stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return ABACUS_NF_EDEVICE;
     float best = 1e30f;
     abacus_nf_tuning best_t = cur;
-    for (const abacus_nf_tuning &t : cand) {
-        if (abacus_nf_set_tuning(h, &t) != ABACUS_NF_OK) continue;
-        rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);  // warm-up (allocates if needed)
-        if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
-        if (rc != ABACUS_NF_OK) break;
+    // time one candidate; keeps the fastest in best / best_t
+    auto trial = [&](const abacus_nf_tuning &t) -> int {
+        if (abacus_nf_set_tuning(h, &t) != ABACUS_NF_OK) return ABACUS_NF_OK;  // invalid combination: skip
+        int r = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);    // warm-up (allocates if needed)
+        if (r == ABACUS_NF_OK) r = abacus_nf_sync(hip_stream);
+        if (r != ABACUS_NF_OK) return r;
         hipEventRecord(e0, st);
-        for (int r = 0; r < reps && rc == ABACUS_NF_OK; r++) rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+        for (int q = 0; q < reps && r == ABACUS_NF_OK; q++) r = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
         hipEventRecord(e1, st);
-        if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
-        if (rc != ABACUS_NF_OK) break;
+        if (r == ABACUS_NF_OK) r = abacus_nf_sync(hip_stream);
+        if (r != ABACUS_NF_OK) return r;
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
             best = ms;
             best_t = t;
         }
-    }
+        return ABACUS_NF_OK;
+    };
+    // stage 1: i-tile (sinks per lane), unroll and register budget on the default j-tile
+    for (int S : {1, 2, 4})
+        for (int U : {1, 2, 4})
+            for (int occ : {0, 6, 8}) {
+                abacus_nf_tuning t = cur;
+                t.sinks_per_lane = S;
+                t.unroll = U;
+                t.occupancy = occ;
+                t.chunk = 256;
+                if (rc == ABACUS_NF_OK) rc = trial(t);
+            }
+    // stage 2: j-tile (LDS chunk) and lane sharing around the best of stage 1
+    const abacus_nf_tuning s1 = best_t;
+    for (int chunk : {128, 512})
+        if (rc == ABACUS_NF_OK) {
+            abacus_nf_tuning t = s1;
+            t.chunk = chunk;
+            rc = trial(t);
+        }
+    const abacus_nf_tuning s2 = best_t;
+    for (int ml : {4, 16})
+        if (rc == ABACUS_NF_OK) {
+            abacus_nf_tuning t = s2;
+            t.max_lanes = ml;
+            rc = trial(t);
+        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc != ABACUS_NF_OK) {
@@ -148,7 +166,8 @@ extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_n
     if (rc != ABACUS_NF_OK) return rc;
     if (cache_path) {
         auto m = read_cache(cache_path);
-        m[key] = {best_t.sinks_per_lane, best_t.chunk, best_t.unroll, best_t.max_lanes, best_t.part_sources};
+        m[key] = {best_t.sinks_per_lane, best_t.chunk, best_t.unroll, best_t.max_lanes, best_t.part_sources,
+                  best_t.occupancy};
         write_cache(cache_path, m);
     }
     if (out) abacus_nf_get_tuning(h, out);

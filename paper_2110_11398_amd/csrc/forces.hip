@@ -147,7 +147,7 @@ __global__ void k_wl_clear(WorkState *ws, int part_iters) {
         ws->base_items = 0;
         ws->split_items = 0;
         ws->n_items = 0;
-        ws->cursor = 0;
+        for (int q = 0; q < kQueues; q++) ws->cursor[q] = 0;
         ws->part_iters = part_iters;
         ws->overflow = 0;
     }
@@ -251,7 +251,7 @@ __global__ void k_wl_classes(WorkState *ws, int64_t item_capacity, const int64_t
     // on overflow nothing is emitted and nothing is computed: the error is
     // reported by abacus_nf_sync and the output is left unwritten
     ws->n_items = over ? 0 : (int32_t)run;
-    ws->cursor = 0;
+    for (int q = 0; q < kQueues; q++) ws->cursor[q] = 0;
     ws->overflow = over ? 1 : 0;
     if (over) atomicCAS(err, 0, ABACUS_NF_ECAPACITY);
 }
@@ -311,6 +311,7 @@ struct KArgs {
     const int64_t *cell_pbase;
     double *partials;
     float *acc;
+    float *rho;
     int R;
     int chunk;      // sources per LDS chunk
     int max_lanes;
@@ -332,25 +333,25 @@ __device__ inline void wave_lds_sync() {
 __device__ inline int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // One FP32 pair term: returns g with d = (dx, dy, dz) = source - sink.
-//   spline : g = min(r^-3, c0 + r2 (c1 r^-1 + c2)); the cubic force polynomial
-//            lies below r^-2 inside eps and above it outside, so the minimum
-//            selects the right branch without a compare.
+//   spline : g = r^-3 for r2 >= eps2, else c0 + r2 (c1 r^-1 + c2) (the cubic
+//            force polynomial divided by r); e2 holds eps2 in cell units.
 //   Plummer: g = (r2 + eps2)^(-3/2).
 template <int KIND>
-__device__ __forceinline__ float pair_g(float dx, float dy, float dz, float c0, float c1, float c2, float e2) {
+__device__ __forceinline__ float pair_g(float dx, float dy, float dz, float c0, float c1, float c2, float e2,
+                                        float &r2) {
     if constexpr (KIND == ABACUS_NF_PLUMMER) {
-        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, e2)));
+        r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, e2)));
         const float ri = __builtin_amdgcn_rsqf(r2);
         const float ri2 = ri * ri;
         return ri2 * ri;
     } else {
-        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, kTiny)));
+        r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, kTiny)));
         const float ri = __builtin_amdgcn_rsqf(r2);
         const float t = __builtin_fmaf(c1, ri, c2);
         const float ri2 = ri * ri;
         const float p = __builtin_fmaf(r2, t, c0);
         const float ri3 = ri2 * ri;
-        return fminf(ri3, p);
+        return r2 < e2 ? p : ri3;
     }
 }
 
@@ -361,8 +362,41 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
     e = (a - (s - bp)) + (b - bp);
 }
 
-template <int KIND, int MODE, int S, int U>
-__global__ __launch_bounds__(kThreads) void k_forces(KArgs a) {
+// U staged sources against the S sinks of this lane.  With KDE, also the
+// density weight max(0, 1 - r^2/b^2) = max(0, kc - r2 * ib2) (r2 carries the
+// pair chain's constant offset, folded into kc).
+template <int KIND, int MODE, int S, int U, bool KDE>
+__device__ __forceinline__ void accumulate(const float4 (&p)[U], const float (&xi)[S], const float (&yi)[S],
+                                           const float (&zi)[S], float c0, float c1, float c2, float e2,
+                                           float ib2, float kc, float (&ax)[S], float (&ay)[S], float (&az)[S],
+                                           double (&dxs)[S], double (&dys)[S], double (&dzs)[S], float (&rh)[S]) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const float dx = p[u].x - xi[s], dy = p[u].y - yi[s], dz = p[u].z - zi[s];
+            float r2;
+            const float gg = pair_g<KIND>(dx, dy, dz, c0, c1, c2, e2, r2);
+            if constexpr (KDE) rh[s] += fmaxf(__builtin_fmaf(-r2, ib2, kc), 0.f);
+            if constexpr (MODE == ABACUS_NF_SUM_FP64) {
+                dxs[s] += (double)(dx * gg);
+                dys[s] += (double)(dy * gg);
+                dzs[s] += (double)(dz * gg);
+            } else {
+                ax[s] = __builtin_fmaf(dx, gg, ax[s]);
+                ay[s] = __builtin_fmaf(dy, gg, ay[s]);
+                az[s] = __builtin_fmaf(dz, gg, az[s]);
+            }
+        }
+    }
+}
+
+// OCC > 0 asks the compiler for at least OCC waves per SIMD (a register budget of
+// 512/OCC VGPRs); OCC = 0 leaves the register budget to the compiler.
+template <int KIND, int MODE, int S, int U, int OCC, bool KDE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, OCC > 0 ? OCC : 8)))
+void k_forces(KArgs a) {
+    constexpr int NC = KDE ? 4 : 3;  // reduced components per sink: acceleration (+ density)
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -375,11 +409,24 @@ __global__ __launch_bounds__(kThreads) void k_forces(KArgs a) {
     const int W = 2 * R + 1;
     const int ncol = W * W;
     const int n_items = a.ws->n_items;
+    const int home = blockIdx.x % kQueues;
+    int queue = 0;  // queues tried so far (own queue first, then the others in turn)
 
     for (;;) {
-        int k = 0;
-        if (lane == 0) k = atomicAdd(&a.ws->cursor, 1);
-        k = sgpr(__shfl(k, 0));
+        // next item: the j-th item of queue x lives in block x + kQueues*(j / kQueueBlock)
+        int k = n_items;
+        while (queue < kQueues) {
+            const int x = (home + queue) % kQueues;
+            int j = 0;
+            if (lane == 0) j = atomicAdd(&a.ws->cursor[x], 1);
+            j = sgpr(__shfl(j, 0));
+            const int64_t idx = ((int64_t)(j / kQueueBlock) * kQueues + x) * kQueueBlock + j % kQueueBlock;
+            if (idx < n_items) {
+                k = (int)idx;
+                break;
+            }
+            queue++;  // queue x is drained (its later indices only grow)
+        }
         if (k >= n_items) break;
         const Item it = a.items[k];
         const int c = sgpr(it.cell);
@@ -434,19 +481,26 @@ __global__ __launch_bounds__(kThreads) void k_forces(KArgs a) {
 
         const int P = a.cell_parts[c];
         const int part = sgpr(it.part);
-        const int j0 = (int)((int64_t)nsrc * part / P);
-        const int j1 = (int)((int64_t)nsrc * (part + 1) / P);
+        // part boundaries: nsrc split into P near-equal contiguous ranges (32-bit arithmetic)
+        const int pq = nsrc / P, pr = nsrc - pq * P;
+        const int j0 = part * pq + min(part, pr);
+        const int j1 = j0 + pq + (part < pr ? 1 : 0);
 
         float ax[S], ay[S], az[S];
         float hx[S], hy[S], hz[S], lx[S], ly[S], lz[S];
         double dxs[S], dys[S], dzs[S];
+        float rh[S];
+        double rhd[S];
 #pragma unroll
         for (int s = 0; s < S; s++) {
             ax[s] = ay[s] = az[s] = 0.f;
             hx[s] = hy[s] = hz[s] = lx[s] = ly[s] = lz[s] = 0.f;
             dxs[s] = dys[s] = dzs[s] = 0.0;
+            rh[s] = 0.f;
+            rhd[s] = 0.0;
         }
         const float c0 = F.c0, c1 = F.c1, c2 = F.c2, e2 = F.eps2;
+        const float ib2 = F.kde_ib2, kc = F.kde_c;
         const int step = L * U;
         const int nmax = (a.chunk / step) * step;
 
@@ -486,26 +540,34 @@ __global__ __launch_bounds__(kThreads) void k_forces(KArgs a) {
 #pragma unroll
                 for (int s = 0; s < S; s++) ax[s] = ay[s] = az[s] = 0.f;
             }
-            for (int q = sub; q < npad; q += step) {
-                float4 p[U];
+            // uniform trip count; one sink group per lane (L == 1) reads with immediate LDS offsets
+            const int iters = npad / step;
+            if (L == 1) {
+                const float4 *sp = stage;
+                for (int it = 0; it < iters; ++it) {
+                    float4 p[U];
 #pragma unroll
-                for (int u = 0; u < U; u++) p[u] = stage[q + u * L];
+                    for (int u = 0; u < U; u++) p[u] = sp[u];
+                    sp += U;
+                    accumulate<KIND, MODE, S, U, KDE>(p, xi, yi, zi, c0, c1, c2, e2, ib2, kc, ax, ay, az, dxs, dys,
+                                                      dzs, rh);
+                }
+            } else {
+                const float4 *sp = stage + sub;
+                for (int it = 0; it < iters; ++it) {
+                    float4 p[U];
 #pragma unroll
-                for (int u = 0; u < U; u++) {
+                    for (int u = 0; u < U; u++) p[u] = sp[u * L];
+                    sp += step;
+                    accumulate<KIND, MODE, S, U, KDE>(p, xi, yi, zi, c0, c1, c2, e2, ib2, kc, ax, ay, az, dxs, dys,
+                                                      dzs, rh);
+                }
+            }
+            if constexpr (KDE && MODE != ABACUS_NF_SUM_FP32) {
 #pragma unroll
-                    for (int s = 0; s < S; s++) {
-                        const float dx = p[u].x - xi[s], dy = p[u].y - yi[s], dz = p[u].z - zi[s];
-                        const float gg = pair_g<KIND>(dx, dy, dz, c0, c1, c2, e2);
-                        if constexpr (MODE == ABACUS_NF_SUM_FP64) {
-                            dxs[s] += (double)(dx * gg);
-                            dys[s] += (double)(dy * gg);
-                            dzs[s] += (double)(dz * gg);
-                        } else {
-                            ax[s] = __builtin_fmaf(dx, gg, ax[s]);
-                            ay[s] = __builtin_fmaf(dy, gg, ay[s]);
-                            az[s] = __builtin_fmaf(dz, gg, az[s]);
-                        }
-                    }
+                for (int s = 0; s < S; s++) {
+                    rhd[s] += (double)rh[s];
+                    rh[s] = 0.f;
                 }
             }
             if constexpr (MODE == ABACUS_NF_SUM_COMP32) {
@@ -524,80 +586,73 @@ __global__ __launch_bounds__(kThreads) void k_forces(KArgs a) {
             f += n;
         }
 
-        // ordered reduction over the L lanes that share each sink, one component at a time
-        const int slot0 = cs0 + t0;
-        const bool split = P > 1;
-        const int64_t pb = split ? a.cell_pbase[c] + (int64_t)part * nc + t0 : 0;
-        double tot[S][3];
-        float totf[S][3];
+        // ordered reduction over the L lanes that share each sink (all components at once)
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-#pragma unroll
-            for (int s = 0; s < S; s++) {
-                if constexpr (MODE == ABACUS_NF_SUM_FP32) {
-                    redf[lane * S + s] = d == 0 ? ax[s] : (d == 1 ? ay[s] : az[s]);
-                } else if constexpr (MODE == ABACUS_NF_SUM_COMP32) {
-                    const float h = d == 0 ? hx[s] : (d == 1 ? hy[s] : hz[s]);
-                    const float l = d == 0 ? lx[s] : (d == 1 ? ly[s] : lz[s]);
-                    red[lane * S + s] = (double)h + (double)l;
-                } else {
-                    red[lane * S + s] = d == 0 ? dxs[s] : (d == 1 ? dys[s] : dzs[s]);
-                }
+        for (int s = 0; s < S; s++) {
+            const int o = (lane * S + s) * NC;
+            if constexpr (MODE == ABACUS_NF_SUM_FP32) {
+                redf[o + 0] = ax[s];
+                redf[o + 1] = ay[s];
+                redf[o + 2] = az[s];
+                if constexpr (KDE) redf[o + 3] = rh[s];
+            } else if constexpr (MODE == ABACUS_NF_SUM_COMP32) {
+                red[o + 0] = (double)hx[s] + (double)lx[s];
+                red[o + 1] = (double)hy[s] + (double)ly[s];
+                red[o + 2] = (double)hz[s] + (double)lz[s];
+                if constexpr (KDE) red[o + 3] = rhd[s];
+            } else {
+                red[o + 0] = dxs[s];
+                red[o + 1] = dys[s];
+                red[o + 2] = dzs[s];
+                if constexpr (KDE) red[o + 3] = rhd[s];
             }
-            wave_lds_sync();
-            if (sub == 0 && g < G) {
-#pragma unroll
-                for (int s = 0; s < S; s++) {
-                    if constexpr (MODE == ABACUS_NF_SUM_FP32) {
-                        float t = 0.f;
-                        for (int q = 0; q < L; q++) t += redf[(g * L + q) * S + s];
-                        totf[s][d] = t;
-                    } else {
-                        double t = 0.0;
-                        for (int q = 0; q < L; q++) t += red[(g * L + q) * S + s];
-                        tot[s][d] = t;
-                    }
-                }
-            }
-            wave_lds_sync();
         }
+        wave_lds_sync();
         if (sub == 0 && g < G) {
-#pragma unroll
+            const bool split = P > 1;
             for (int s = 0; s < S; s++) {
                 const int idx = g * S + s;
-                if (idx < nt) {
-                    if (!split) {
-                        const int64_t i = a.perm[slot0 + idx];
-                        float *out = a.acc + 3 * i;
+                if (idx >= nt) break;
+                const int base = (g * L * S + s) * NC;
+                if (!split) {
+                    const int64_t i = a.perm[cs0 + t0 + idx];
+                    float *out = a.acc + 3 * i;
+                    for (int d = 0; d < NC; d++) {
+                        float v;
                         if constexpr (MODE == ABACUS_NF_SUM_FP32) {
-                            out[0] = totf[s][0] * F.scalef;
-                            out[1] = totf[s][1] * F.scalef;
-                            out[2] = totf[s][2] * F.scalef;
+                            float t = 0.f;
+                            for (int q = 0; q < L; q++) t += redf[base + q * S * NC + d];
+                            v = d < 3 ? t * F.scalef : t;
                         } else {
-                            out[0] = (float)(tot[s][0] * F.scale);
-                            out[1] = (float)(tot[s][1] * F.scale);
-                            out[2] = (float)(tot[s][2] * F.scale);
+                            double t = 0.0;
+                            for (int q = 0; q < L; q++) t += red[base + q * S * NC + d];
+                            v = (float)(d < 3 ? t * F.scale : t);
                         }
-                    } else {
-                        double *out = a.partials + 3 * (pb + idx);
+                        if (d < 3) out[d] = v;
+                        else a.rho[i] = v;
+                    }
+                } else {
+                    double *out = a.partials + (int64_t)NC * (a.cell_pbase[c] + (int64_t)part * nc + t0 + idx);
+                    for (int d = 0; d < NC; d++) {
                         if constexpr (MODE == ABACUS_NF_SUM_FP32) {
-                            out[0] = totf[s][0];
-                            out[1] = totf[s][1];
-                            out[2] = totf[s][2];
+                            float t = 0.f;
+                            for (int q = 0; q < L; q++) t += redf[base + q * S * NC + d];
+                            out[d] = t;
                         } else {
-                            out[0] = tot[s][0];
-                            out[1] = tot[s][1];
-                            out[2] = tot[s][2];
+                            double t = 0.0;
+                            for (int q = 0; q < L; q++) t += red[base + q * S * NC + d];
+                            out[d] = t;
                         }
                     }
                 }
             }
         }
+        wave_lds_sync();
     }
 }
 
 // Sinks whose source list was split: add the parts in order and write the result.
-template <int MODE>
+template <int MODE, int NC>
 __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ ws, int64_t partial_capacity,
                                                   const int32_t *__restrict__ keys, const int32_t *__restrict__ cs,
                                                   const int32_t *__restrict__ perm,
@@ -606,7 +661,7 @@ __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ 
                                                   const double *__restrict__ partials,
                                                   const BoxDev *__restrict__ boxes, int n_boxes,
                                                   const ForceBox *__restrict__ fbox, float *__restrict__ acc,
-                                                  int64_t n) {
+                                                  float *__restrict__ rho, int64_t n) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n || ws->overflow) return;
     const int32_t c = keys[s];
@@ -617,17 +672,20 @@ __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ 
     if (base + (int64_t)(P - 1) * nc >= partial_capacity) return;
     const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, c) : 0;
     const ForceBox F = fbox[b];
-    float *out = acc + 3 * (int64_t)perm[s];
-    for (int d = 0; d < 3; d++) {
+    const int64_t i = perm[s];
+    for (int d = 0; d < NC; d++) {
+        float v;
         if constexpr (MODE == ABACUS_NF_SUM_FP32) {
             float t = 0.f;
-            for (int p = 0; p < P; p++) t += (float)partials[3 * (base + (int64_t)p * nc) + d];
-            out[d] = t * F.scalef;
+            for (int p = 0; p < P; p++) t += (float)partials[NC * (base + (int64_t)p * nc) + d];
+            v = d < 3 ? t * F.scalef : t;
         } else {
             double t = 0.0;
-            for (int p = 0; p < P; p++) t += partials[3 * (base + (int64_t)p * nc) + d];
-            out[d] = (float)(t * F.scale);
+            for (int p = 0; p < P; p++) t += partials[NC * (base + (int64_t)p * nc) + d];
+            v = (float)(d < 3 ? t * F.scale : t);
         }
+        if (d < 3) acc[3 * i + d] = v;
+        else rho[i] = v;
     }
 }
 
@@ -635,41 +693,59 @@ __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ 
 
 typedef void (*ForcesKernel)(KArgs);
 
-template <int KIND, int MODE, int S>
-ForcesKernel pick_u(int U) {
+template <int KIND, int MODE, int S, int U, bool KDE>
+ForcesKernel pick_occ(int occ) {
+    if constexpr (KDE) {  // density variants: compiler's register budget or 8 waves per SIMD
+        return occ == 8 ? k_forces<KIND, MODE, S, U, 8, true> : k_forces<KIND, MODE, S, U, 0, true>;
+    } else {
+        switch (occ) {
+            case 6: return k_forces<KIND, MODE, S, U, 6, false>;
+            case 8: return k_forces<KIND, MODE, S, U, 8, false>;
+            default: return k_forces<KIND, MODE, S, U, 0, false>;
+        }
+    }
+}
+
+template <int KIND, int MODE, int S, bool KDE>
+ForcesKernel pick_u(int U, int occ) {
     switch (U) {
-        case 1: return k_forces<KIND, MODE, S, 1>;
-        case 4: return k_forces<KIND, MODE, S, 4>;
-        default: return k_forces<KIND, MODE, S, 2>;
+        case 1: return pick_occ<KIND, MODE, S, 1, KDE>(occ);
+        case 4:
+            if constexpr (!KDE) return pick_occ<KIND, MODE, S, 4, KDE>(occ);
+            else return pick_occ<KIND, MODE, S, 2, KDE>(occ);
+        default: return pick_occ<KIND, MODE, S, 2, KDE>(occ);
     }
 }
 
-template <int KIND, int MODE>
-ForcesKernel pick_s(int S, int U) {
+template <int KIND, int MODE, bool KDE>
+ForcesKernel pick_s(int S, int U, int occ) {
     switch (S) {
-        case 1: return pick_u<KIND, MODE, 1>(U);
-        case 4: return pick_u<KIND, MODE, 4>(U);
-        default: return pick_u<KIND, MODE, 2>(U);
+        case 1: return pick_u<KIND, MODE, 1, KDE>(U, occ);
+        case 4: return pick_u<KIND, MODE, 4, KDE>(U, occ);
+        default: return pick_u<KIND, MODE, 2, KDE>(U, occ);
     }
 }
 
-template <int KIND>
-ForcesKernel pick_mode(int mode, int S, int U) {
+template <int KIND, bool KDE>
+ForcesKernel pick_mode(int mode, int S, int U, int occ) {
     switch (mode) {
-        case ABACUS_NF_SUM_COMP32: return pick_s<KIND, ABACUS_NF_SUM_COMP32>(S, U);
-        case ABACUS_NF_SUM_FP64: return pick_s<KIND, ABACUS_NF_SUM_FP64>(S, U);
-        default: return pick_s<KIND, ABACUS_NF_SUM_FP32>(S, U);
+        case ABACUS_NF_SUM_COMP32: return pick_s<KIND, ABACUS_NF_SUM_COMP32, KDE>(S, U, occ);
+        case ABACUS_NF_SUM_FP64: return pick_s<KIND, ABACUS_NF_SUM_FP64, KDE>(S, U, occ);
+        default: return pick_s<KIND, ABACUS_NF_SUM_FP32, KDE>(S, U, occ);
     }
 }
 
-ForcesKernel pick_kernel(abacus_nf_kind kind, abacus_nf_sum mode, int S, int U) {
-    return kind == ABACUS_NF_PLUMMER ? pick_mode<ABACUS_NF_PLUMMER>(mode, S, U)
-                                     : pick_mode<ABACUS_NF_SPLINE>(mode, S, U);
+ForcesKernel pick_kernel(abacus_nf_kind kind, abacus_nf_sum mode, int S, int U, int occ, bool kde) {
+    if (kde)
+        return kind == ABACUS_NF_PLUMMER ? pick_mode<ABACUS_NF_PLUMMER, true>(mode, S, U, occ)
+                                         : pick_mode<ABACUS_NF_SPLINE, true>(mode, S, U, occ);
+    return kind == ABACUS_NF_PLUMMER ? pick_mode<ABACUS_NF_PLUMMER, false>(mode, S, U, occ)
+                                     : pick_mode<ABACUS_NF_SPLINE, false>(mode, S, U, occ);
 }
 
 size_t region_bytes(const abacus_nf_tuning &t) {
     size_t stage = (size_t)t.chunk * sizeof(float4);
-    size_t red = (size_t)64 * t.sinks_per_lane * sizeof(double);
+    size_t red = (size_t)64 * t.sinks_per_lane * 4 * sizeof(double);
     size_t main = stage > red ? stage : red;
     return (main + (size_t)2 * 49 * sizeof(Seg) + 15) & ~(size_t)15;
 }
@@ -678,8 +754,8 @@ size_t region_bytes(const abacus_nf_tuning &t) {
 
 // ---------------------------------------------------------------- host side
 
-hipError_t launch_set_force_boxes(const double *eps, const double *gm, const abacus_nf_box *boxes, int n_boxes,
-                                  ForceBox *dst, hipStream_t st) {
+hipError_t launch_set_force_boxes(const double *eps, const double *gm, const double *kde_b, abacus_nf_kind kind,
+                                  const abacus_nf_box *boxes, int n_boxes, ForceBox *dst, hipStream_t st) {
     for (int first = 0; first < n_boxes; first += kFBoxChunk) {
         FBoxChunk ch;
         memset(&ch, 0, sizeof(ch));
@@ -696,6 +772,16 @@ hipError_t launch_set_force_boxes(const double *eps, const double *gm, const aba
             f.eps2 = (float)(e * e);
             f.scale = gm[b] / (w * w);
             f.scalef = (float)f.scale;
+            if (kde_b) {
+                const double bc = kde_b[b] / w;
+                const double ib2 = 1.0 / (bc * bc);
+                const double offset = kind == ABACUS_NF_PLUMMER ? (double)f.eps2 : (double)kTiny;
+                f.kde_ib2 = (float)ib2;
+                f.kde_c = (float)(1.0 + offset * ib2);
+            } else {
+                f.kde_ib2 = 0.f;
+                f.kde_c = 0.f;
+            }
             f.pad = 0;
         }
         hipLaunchKernelGGL(k_set_fbox, dim3(1), dim3(kFBoxChunk), 0, st, ch, dst);
@@ -734,8 +820,8 @@ hipError_t build_work_list(const ForcesArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-int forces_grid(const abacus_nf_tuning &t, abacus_nf_kind kind, abacus_nf_sum mode, int device) {
-    ForcesKernel kfn = pick_kernel(kind, mode, t.sinks_per_lane, t.unroll);
+int forces_grid(const abacus_nf_tuning &t, abacus_nf_kind kind, abacus_nf_sum mode, bool kde, int device) {
+    ForcesKernel kfn = pick_kernel(kind, mode, t.sinks_per_lane, t.unroll, t.occupancy, kde);
     const size_t lds = region_bytes(t) * kWaves;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kfn, kThreads, lds) != hipSuccess ||
@@ -764,11 +850,13 @@ hipError_t launch_forces(const ForcesArgs &a, hipStream_t st) {
     k.cell_pbase = a.cell_pbase;
     k.partials = a.partials;
     k.acc = a.acc;
+    k.rho = a.rho;
     k.R = a.R;
     k.chunk = a.tune.chunk;
     k.max_lanes = a.tune.max_lanes;
     k.region = (int)region_bytes(a.tune);
-    ForcesKernel kfn = pick_kernel(a.kind, a.mode, a.tune.sinks_per_lane, a.tune.unroll);
+    ForcesKernel kfn = pick_kernel(a.kind, a.mode, a.tune.sinks_per_lane, a.tune.unroll, a.tune.occupancy,
+                                   a.rho != nullptr);
     hipLaunchKernelGGL(kfn, dim3(a.grid), dim3(kThreads), (size_t)k.region * kWaves, st, k);
     return hipGetLastError();
 }
@@ -776,14 +864,11 @@ hipError_t launch_forces(const ForcesArgs &a, hipStream_t st) {
 hipError_t launch_finalize(const ForcesArgs &a, hipStream_t st) {
     if (a.n_total <= 0) return hipSuccess;
     const unsigned gn = grid_for(a.n_total, 256);
-    if (a.mode == ABACUS_NF_SUM_FP32)
-        hipLaunchKernelGGL(k_finalize<ABACUS_NF_SUM_FP32>, dim3(gn), dim3(256), 0, st, a.ws, a.partial_capacity,
-                           a.keys, a.cell_start, a.perm,
-                           a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.n_total);
-    else
-        hipLaunchKernelGGL(k_finalize<ABACUS_NF_SUM_FP64>, dim3(gn), dim3(256), 0, st, a.ws, a.partial_capacity,
-                           a.keys, a.cell_start, a.perm,
-                           a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.n_total);
+    const bool f32 = a.mode == ABACUS_NF_SUM_FP32, kde = a.rho != nullptr;
+    auto kfn = f32 ? (kde ? k_finalize<ABACUS_NF_SUM_FP32, 4> : k_finalize<ABACUS_NF_SUM_FP32, 3>)
+                   : (kde ? k_finalize<ABACUS_NF_SUM_FP64, 4> : k_finalize<ABACUS_NF_SUM_FP64, 3>);
+    hipLaunchKernelGGL(kfn, dim3(gn), dim3(256), 0, st, a.ws, a.partial_capacity, a.keys, a.cell_start, a.perm,
+                       a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.rho, a.n_total);
     return hipGetLastError();
 }
 

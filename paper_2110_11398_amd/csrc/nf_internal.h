@@ -24,6 +24,8 @@ struct ForceBox {
     float eps2;         // Plummer: g = (r2 + eps2)^(-3/2)
     double scale;       // G*m / w^2: converts a cell-unit sum into an acceleration
     float scalef;       // the same in FP32 (plain FP32 mode)
+    float kde_ib2;      // density: weight = max(0, kde_c - r2 * kde_ib2), kde_ib2 = 1/b^2 (cell units)
+    float kde_c;        // 1 + (offset added to r2 in the pair chain) * kde_ib2
     int32_t pad;
 };
 
@@ -34,13 +36,21 @@ struct Item {
 };
 
 constexpr int kNumClasses = 64;
+// The persistent kernel drains the item list through kQueues queues: the list
+// is cut into blocks of kQueueBlock consecutive items (spatially close cells of
+// one cost class), block b belongs to queue b % kQueues, and a workgroup starts
+// on queue blockIdx % kQueues -- the compute die (XCD) the hardware dispatches
+// it to -- and steals from the other queues once its own is empty.  Neighbouring
+// cells then share one XCD's L2.
+constexpr int kQueues = 8;
+constexpr int kQueueBlock = 32;
 
 // Device-side state of the work list of one forces call.
 struct WorkState {
     unsigned long long interactions;  // sum over cells of n_c * sources(c)
     unsigned long long part_demand;   // partial slots needed at the base part size
     int32_t n_items;                  // items emitted (clamped to the capacity)
-    int32_t cursor;                   // next item for the persistent kernel
+    int32_t cursor[kQueues];          // next item of each queue of the persistent kernel
     int32_t part_iters;               // effective part length (source iterations per lane)
     int32_t overflow;                 // non-zero when a list outgrew its capacity
     unsigned long long base_items;    // items with every source list unsplit
@@ -133,6 +143,7 @@ struct ForcesArgs {
     double *partials;
     int64_t partial_capacity;
     float *acc;
+    float *rho;      // density output (nullptr: forces only)
     int *err;
     abacus_nf_kind kind;
     abacus_nf_sum mode;
@@ -141,12 +152,12 @@ struct ForcesArgs {
     void *scan_temp;
 };
 
-hipError_t launch_set_force_boxes(const double *eps, const double *gm, const abacus_nf_box *boxes, int n_boxes,
-                                  ForceBox *dst, hipStream_t st);
+hipError_t launch_set_force_boxes(const double *eps, const double *gm, const double *kde_b, abacus_nf_kind kind,
+                                  const abacus_nf_box *boxes, int n_boxes, ForceBox *dst, hipStream_t st);
 hipError_t build_work_list(const ForcesArgs &a, hipStream_t st);
 hipError_t launch_forces(const ForcesArgs &a, hipStream_t st);
 hipError_t launch_finalize(const ForcesArgs &a, hipStream_t st);
-int forces_grid(const abacus_nf_tuning &t, abacus_nf_kind kind, abacus_nf_sum mode, int device);
+int forces_grid(const abacus_nf_tuning &t, abacus_nf_kind kind, abacus_nf_sum mode, bool kde, int device);
 hipError_t launch_count_interactions(const ForcesArgs &a, hipStream_t st);
 
 }  // namespace anf

@@ -176,6 +176,8 @@ def test_modes_order_of_accuracy(nf, tiny):
     dict(sinks_per_lane=4, unroll=4, chunk=256, max_lanes=1),
     dict(sinks_per_lane=2, unroll=2, chunk=128, max_lanes=3),
     dict(sinks_per_lane=2, unroll=1, part_sources=1024),
+    dict(sinks_per_lane=2, unroll=2, occupancy=8),
+    dict(sinks_per_lane=4, unroll=1, occupancy=6, chunk=128),
 ])
 def test_tiling_variants(nf, tiny, tuning):
     b, ref = tiny
@@ -332,6 +334,52 @@ def test_late_time_scaled_sampled(nf):
         c.free()
 
 
+# ---------------------------------------------------------------- HIP graph capture
+
+def test_graph_capture_and_replay(nf):
+    """build_cells + forces captured once in a HIP graph; every replay (with eager work and
+    synchronisations in between, and fresh positions copied in) equals the eager result."""
+    w = gen.workload("batched", n_boxes=5, lo=16 ** 3, hi=32 ** 3)
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    eps, gm = [b.eps for b in w.boxes], [b.gm for b in w.boxes]
+    p0 = w.concat_positions()
+    rng = np.random.default_rng(3)
+    p1 = ((p0.astype(np.float64) + 0.01 * rng.standard_normal(p0.shape)) % 1.0).astype(np.float32)
+    p1[p1 >= 1.0] = 0.0
+    pos = torch.from_numpy(p0).cuda()
+    acc = torch.zeros((len(p0), 3), dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        cells = nf.build_cells(pos, boxes, 2)
+        cells.forces(eps, gm, SPLINE, 1, acc)
+        nf.sync(side)
+    torch.cuda.current_stream().wait_stream(side)
+    eager = {}
+    for k, p in enumerate((p0, p1)):
+        pos.copy_(torch.from_numpy(p).cuda())
+        nf.build_cells(pos, boxes, 2, cells=cells)
+        cells.forces(eps, gm, SPLINE, 1, acc)
+        nf.sync()
+        eager[k] = acc.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        nf.build_cells(pos, boxes, 2, cells=cells)
+        cells.forces(eps, gm, SPLINE, 1, acc)
+    for rep in range(4):
+        k = rep % 2
+        pos.copy_(torch.from_numpy((p0, p1)[k]).cuda())
+        acc.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        nf.sync()
+        assert torch.equal(acc, eager[k]), f"replay {rep}"
+        del junk
+    cells.free()
+
+
 # ---------------------------------------------------------------- device-side errors
 
 def test_nonfinite_position_is_reported(nf):
@@ -367,9 +415,76 @@ def test_bad_tuning_is_rejected(nf):
     p = torch.rand((100, 3), device="cuda")
     c = nf.build_cells(p, [(100, 1.0, 5)], 2)
     for bad in (dict(sinks_per_lane=3), dict(unroll=8), dict(chunk=100), dict(chunk=64, unroll=2), dict(chunk=1024),
-                dict(max_lanes=65), dict(part_sources=10)):
+                dict(max_lanes=65), dict(part_sources=10), dict(occupancy=5), dict(reserved=1)):
         with pytest.raises(nf.NearFieldError):
             c.set_tuning(**bad)
     with pytest.raises(nf.NearFieldError):
         c.forces([1e-9], [1.0])   # eps below 1e-5 cell widths
+    c.free()
+
+
+# ---------------------------------------------------------------- fused kernel density estimate (Sec. 3.4)
+
+def run_density(nf, pos_np, boxes, eps, gm, bs, kind=SPLINE, mode=1, tuning=None):
+    pos = torch.from_numpy(np.ascontiguousarray(pos_np, dtype=np.float32)).cuda()
+    c = nf.build_cells(pos, boxes, 2)
+    if tuning:
+        c.set_tuning(**tuning)
+    acc, rho = c.forces_density(eps, gm, bs, kind, mode)
+    nf.sync()
+    return acc.cpu().numpy().astype(np.float64), rho.cpu().numpy().astype(np.float64), c
+
+
+def check_density(rho, ref, what):
+    err = np.abs(rho - ref) / ref
+    print(f"{what}: n={rho.size} max rel err {err.max():.3e} mean rho {ref.mean():.3f}", flush=True)
+    assert np.all(ref >= 1.0)          # the self pair
+    assert err.max() <= 2e-5, what
+
+
+@pytest.mark.parametrize("kind", [SPLINE, PLUMMER])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_density_tiny(nf, tiny, kind, mode):
+    b, ref = tiny
+    bk = 0.4 * (1.0 / 32) * 4          # larger than the paper's 0.4 spacing so most particles see neighbours
+    a, rho, c = run_density(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], [bk], kind, mode)
+    check_density(rho, oracle.density(b.pos, b.box, b.K, 2, bk), f"density tiny kind={kind} mode={mode}")
+    check(a, ref[kind][0], ref[kind][2], f"forces with density kind={kind} mode={mode}")
+    c.free()
+
+
+def test_density_clustered_split_parts(nf):
+    """Heavy halo cells with split source lists: the density goes through the partial slots too."""
+    rng = np.random.default_rng(21)
+    p = np.concatenate([rng.random((20000, 3)), 0.5 + 0.004 * rng.standard_normal((20000, 3))]) % 1.0
+    p = p.astype(np.float32)
+    spacing = 1.0 / len(p) ** (1 / 3)
+    bk = 0.4 * spacing
+    for mode in (0, 1):
+        a, rho, c = run_density(nf, p, [(len(p), 1.0, 8)], [spacing / 40], [1.0 / len(p)], [bk], SPLINE, mode,
+                                tuning=dict(part_sources=1024))
+        check_density(rho, oracle.density(p, 1.0, 8, 2, bk), f"density split mode={mode}")
+        c.free()
+
+
+def test_density_batched_boxes(nf):
+    w = gen.workload("batched", n_boxes=4, lo=20 ** 3, hi=32 ** 3)
+    pos = w.concat_positions()
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    bs = [0.4 * b.n ** (-1 / 3) for b in w.boxes]
+    a, rho, c = run_density(nf, pos, boxes, [b.eps for b in w.boxes], [b.gm for b in w.boxes], bs, SPLINE, 1)
+    off = 0
+    for bx, bk in zip(w.boxes, bs):
+        check_density(rho[off:off + bx.n], oracle.density(bx.pos, bx.box, bx.K, 2, bk), f"density box n={bx.n}")
+        off += bx.n
+    c.free()
+
+
+def test_density_rejects_bad_radius(nf):
+    p = torch.rand((1000, 3), device="cuda")
+    c = nf.build_cells(p, [(1000, 1.0, 5)], 2)
+    with pytest.raises(nf.NearFieldError):
+        c.forces_density([0.01], [1.0], [0.5])      # b = 2.5 cell widths > R
+    with pytest.raises(nf.NearFieldError):
+        c.forces_density([0.01], [1.0], [1e-9])
     c.free()

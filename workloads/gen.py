@@ -142,14 +142,32 @@ def plummer_halo_positions(rng: np.random.Generator, counts: np.ndarray, scale: 
     return out
 
 
+_VERBOSE = False
+
+
+def set_verbose(on: bool = True):
+    """Print the progress of long generations to stderr."""
+    global _VERBOSE
+    _VERBOSE = bool(on)
+
+
+def _say(msg: str):
+    if _VERBOSE:
+        import sys
+        import time
+        print(f"[gen {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def _clustered_box(seed: int, n: int, K: int, frac_halo: float, n_halos: int,
                    scale_cells, box: float = 1.0, shuffle: bool = True) -> np.ndarray:
     """Uniform background plus Plummer halos; returns float32 positions."""
     rng = np.random.default_rng(seed)
     n_h = int(round(n * frac_halo)) if n_halos > 0 else 0
     n_u = n - n_h
+    _say(f"box seed {seed}: {n_u} uniform")
     parts = [uniform_positions(rng, n_u, box)]
     if n_h > 0:
+        _say(f"box seed {seed}: {n_h} in {n_halos} halos")
         masses = power_law_masses(rng, n_halos)
         counts = largest_remainder(masses, n_h)
         w = box / K
@@ -158,8 +176,10 @@ def _clustered_box(seed: int, n: int, K: int, frac_halo: float, n_halos: int,
         else:
             a = np.full(n_halos, float(scale_cells) * w)
         parts.append(plummer_halo_positions(rng, counts, a, box))
+    _say(f"box seed {seed}: wrap and cast")
     pos = _finish(np.concatenate(parts, axis=0), box)
     if shuffle and n > 1:
+        _say(f"box seed {seed}: shuffle")
         pos = pos[rng.permutation(n)]
     return pos
 
