@@ -9,6 +9,8 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   Sec. 2.4 / Sec. 5.2, the cell rule, and an exact pair counter.
 * the kernel density estimate fused into the same pass (Sec. 3.4), weight
   max(0, 1 - r^2/b^2) over the near field, self pair included (a reading).
+* cell multipoles (Sec. 3.1, order p = 8): complete Cartesian moments about
+  each cell centre, positions in cell widths (a reading of the basis).
 * ``brute.py``: an independent NumPy all-pairs x 27-image enumeration for tiny
   inputs, which keeps a pair exactly when its cell offset lies in [-R, R]^3.
 
@@ -17,7 +19,9 @@ is pinned to the reading (value, slope and curvature matching 1/r^2 at r=eps)
 but "parity unpinned" against the original code.
 """
 from .oracle import (lib_path, build, compile_oracle, Oracle, default, bin_cells, kernel_g,
-                     forces, count_pairs, density, forces_boxes, SOURCE, SPLINE, PLUMMER)
+                     forces, count_pairs, density, multipoles, multipole_exponents, forces_boxes, SOURCE,
+                     SPLINE, PLUMMER)
 
 __all__ = ["lib_path", "build", "compile_oracle", "Oracle", "default", "bin_cells", "kernel_g",
-           "forces", "count_pairs", "density", "forces_boxes", "SOURCE", "SPLINE", "PLUMMER"]
+           "forces", "count_pairs", "density", "multipoles", "multipole_exponents", "forces_boxes", "SOURCE",
+           "SPLINE", "PLUMMER"]

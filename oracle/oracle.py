@@ -59,8 +59,9 @@ class Oracle:
         lib.oracle_nf_forces.argtypes = [vp, c_i64, c_d, ci, ci, c_d, ci, c_d, vp, c_i64, ci, ci, vp, vp, vp]
         lib.oracle_nf_count_pairs.argtypes = [vp, c_i64, c_d, ci, ci, vp]
         lib.oracle_nf_density.argtypes = [vp, c_i64, c_d, ci, ci, c_d, vp, c_i64, ci, vp]
+        lib.oracle_nf_multipoles.argtypes = [vp, c_i64, c_d, ci, ci, c_d, vp]
         for f in (lib.oracle_nf_bin, lib.oracle_nf_kernel, lib.oracle_nf_forces, lib.oracle_nf_count_pairs,
-                  lib.oracle_nf_density):
+                  lib.oracle_nf_density, lib.oracle_nf_multipoles):
             f.restype = ctypes.c_int
         self.lib = lib
         self.path = path
@@ -122,6 +123,15 @@ class Oracle:
                                           sp, m, int(threads), rho.ctypes.data if m else None), "density")
         return rho
 
+    def multipoles(self, pos, box: float, K: int, p: int = 8, m: float = 1.0) -> np.ndarray:
+        """Complete Cartesian moments about each cell centre in cell widths, [K^3, (p+1)(p+2)(p+3)/6] FP64."""
+        q = _pos32(pos)
+        ncomp = (p + 1) * (p + 2) * (p + 3) // 6
+        out = np.zeros((K ** 3, ncomp), dtype=np.float64)
+        _check(self.lib.oracle_nf_multipoles(q.ctypes.data if q.shape[0] else None, q.shape[0], float(box), int(K),
+                                             int(p), float(m), out.ctypes.data), "multipoles")
+        return out
+
     def count_pairs(self, pos, box: float, K: int, R: int = 2) -> int:
         """Exact number of (sink, source) pairs, self pairs included, from cell occupancy."""
         p = _pos32(pos)
@@ -162,6 +172,15 @@ def count_pairs(pos, box, K, R=2):
 
 def density(pos, box, K, R, b, sinks=None, threads=0):
     return default().density(pos, box, K, R, b, sinks, threads)
+
+
+def multipoles(pos, box, K, p=8, m=1.0):
+    return default().multipoles(pos, box, K, p, m)
+
+
+def multipole_exponents(p: int):
+    """(a, b, k) of each component, in the order used by the multipole arrays."""
+    return [(a, b, n - a - b) for n in range(p + 1) for a in range(n, -1, -1) for b in range(n - a, -1, -1)]
 
 
 def forces_boxes(boxes: Sequence, R: int = 2, kind: int = SPLINE, threads: int = 0) -> np.ndarray:

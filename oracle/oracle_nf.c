@@ -40,6 +40,10 @@
  * of the mean interparticle spacing).  The self pair is included (weight 1):
  * the paper does not say, and this is the reading used here.
  *
+ * Cell multipoles (Sec. 3.1: the far field starts from the multipole moments
+ * of the mass in each cell, order p = 8): complete Cartesian moments about the
+ * cell centre in cell widths (see oracle_nf_multipoles).
+ *
  * Coincident particles (including the self pair) contribute exactly zero force.
  * Sums are plain FP64 in a fixed order (neighbour cells in lexicographic
  * (dx,dy,dz) order, sources in input order within a cell), or Neumaier
@@ -316,5 +320,48 @@ int oracle_nf_density(const float *pos, int64_t n, double L, int K, int R, doubl
         rho[q] = sum;
     }
     free(cell); free(xt); free(start); free(list); free(fill);
+    return ORACLE_OK;
+}
+
+/*
+ * Cell multipole moments (Sec. 3.1: the far field is built from the multipole
+ * moments of the mass in each cell, order p = 8 for AbacusSummit).  Reading:
+ * the complete Cartesian moments about the cell centre, in cell widths,
+ *     M_c^{(a,b,k)} = m * sum_{j in c} u_j^a v_j^b w_j^k,   a + b + k <= p,
+ * with (u, v, w) = (xt*K/L - (c + 1/2)) per axis, the position relative to the
+ * centre of its cell in cell widths (FP64 from the FP32 input).  Components are
+ * ordered by degree n = 0..p, then a = n..0, then b = n-a..0 (k = n-a-b).
+ *   out [K^3][ncomp] float64, ncomp = (p+1)(p+2)(p+3)/6.
+ */
+int oracle_nf_multipoles(const float *pos, int64_t n, double L, int K, int p, double m, double *out) {
+    if (n < 0 || !(L > 0) || K < 1 || p < 0 || p > 16 || (n > 0 && !pos) || !out) return ORACLE_EINVAL;
+    const int64_t ncell = (int64_t)K * K * K;
+    const int ncomp = (p + 1) * (p + 2) * (p + 3) / 6;
+    const double s = (double)K / L;
+    memset(out, 0, sizeof(double) * (size_t)ncell * (size_t)ncomp);
+    double pu[17], pv[17], pw[17];
+    for (int64_t i = 0; i < n; i++) {
+        double t[3];
+        int c[3];
+        for (int d = 0; d < 3; d++) {
+            double xt;
+            c[d] = axis_cell((double)pos[3 * i + d], L, s, K, &xt);
+            t[d] = xt * s - ((double)c[d] + 0.5);
+        }
+        pu[0] = pv[0] = pw[0] = 1.0;
+        for (int q = 1; q <= p; q++) {
+            pu[q] = pu[q - 1] * t[0];
+            pv[q] = pv[q - 1] * t[1];
+            pw[q] = pw[q - 1] * t[2];
+        }
+        double *o = out + (((int64_t)c[0] * K + c[1]) * K + c[2]) * ncomp;
+        int idx = 0;
+        for (int deg = 0; deg <= p; deg++)
+            for (int a = deg; a >= 0; a--)
+                for (int b = deg - a; b >= 0; b--) {
+                    const int k = deg - a - b;
+                    o[idx++] += m * (pu[a] * pv[b] * pw[k]);
+                }
+    }
     return ORACLE_OK;
 }

@@ -24,6 +24,9 @@ MUTANTS = {
     "neighbour_x_wrap": ("else if (ex >= K) { ex -= K; sx = 1; }", "else if (ex >= K) { ex -= K; sx = 0; }"),
     "density_weight_power": ("double w = 1.0 - (ddx * ddx + ddy * ddy + ddz * ddz) / b2;",
                              "double w = 1.0 - sqrt(ddx * ddx + ddy * ddy + ddz * ddz) / b;"),
+    "multipole_centre": ("t[d] = xt * s - ((double)c[d] + 0.5);", "t[d] = xt * s - (double)c[d];"),
+    "multipole_power": ("pw[q] = pw[q - 1] * t[2];", "pw[q] = pw[q - 1] * t[1];"),
+    "multipole_order": ("for (int b = deg - a; b >= 0; b--) {", "for (int b = 0; b <= deg - a; b++) {"),
     "density_self_excluded": ("if (w > 0.0) sum += w;", "if (w > 0.0 && w < 1.0) sum += w;"),
     "density_image_dropped": ("double ddz = (xt[3 * j + 2] + sz * L) - zi;\n                        double w",
                               "double ddz = xt[3 * j + 2] - zi;\n                        double w"),
@@ -60,6 +63,11 @@ def battery(o: oracle.Oracle) -> list:
     pos[:2] = [[0.5, 0.5, 0.001], [0.5, 0.5, 0.999]]
     if not np.allclose(o.density(pos, 1.0, 5, 2, 0.12), brute_density(pos, 1.0, 5, 2, 0.12), rtol=1e-12, atol=0):
         bad.append("density")
+    from oracle import multipole_exponents
+    q = np.array([[(2.5 + 0.25) / 4, (1.5 - 0.375) / 4, (0.5 + 0.125) / 4]], np.float32)
+    M = o.multipoles(q, 1.0, 4, 8, 1.0)[(2 * 4 + 1) * 4 + 0]
+    if not np.array_equal(M, [0.25 ** a * (-0.375) ** b * 0.125 ** k for a, b, k in multipole_exponents(8)]):
+        bad.append("multipoles")
     return bad
 
 

@@ -291,3 +291,77 @@ def test_density_lattice(orc):
     b = 1.25 * a
     rho = orc.density(pos, m * a, K, 2, b)
     np.testing.assert_allclose(rho, 1 + 6 * (1 - 1 / 1.25 ** 2), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- cell multipoles (Sec. 3.1, order 8)
+
+def test_multipole_component_order_and_count():
+    from oracle import multipole_exponents
+    e = multipole_exponents(8)
+    assert len(e) == 165 == len(set(e))
+    assert e[0] == (0, 0, 0) and e[1:4] == [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    assert all(sum(t) <= 8 for t in e)
+
+
+def test_multipoles_single_particle_closed_form(orc):
+    """One particle at cell-relative (u, v, w): every moment is m u^a v^b w^k (dyadic values, exact)."""
+    from oracle import multipole_exponents
+    K, L = 4, 1.0
+    u, v, w = 0.25, -0.375, 0.125
+    cell = (2, 1, 3)
+    pos = np.array([[(cell[0] + 0.5 + u) / K, (cell[1] + 0.5 + v) / K, (cell[2] + 0.5 + w) / K]], np.float32)
+    M = orc.multipoles(pos, L, K, 8, 2.0)
+    lin = (cell[0] * K + cell[1]) * K + cell[2]
+    want = np.array([2.0 * u ** a * v ** b * w ** k for a, b, k in multipole_exponents(8)])
+    assert np.array_equal(M[lin], want)
+    assert np.count_nonzero(np.delete(M, lin, axis=0)) == 0
+
+
+def test_multipoles_symmetric_pairs_cancel_odd_orders(orc):
+    """Pairs mirrored through the cell centre: all odd-degree moments vanish, even ones double."""
+    from oracle import multipole_exponents
+    K = 4                                                                  # dyadic cell width: exact positions
+    rng = np.random.default_rng(2)
+    off = (rng.integers(-2 ** 10, 2 ** 10, size=(50, 3)) / 2 ** 12)        # dyadic offsets, |off| < 1/4
+    centre = np.array([1.5, 1.5, 1.5])
+    pos = np.concatenate([centre + off, centre - off]) / K
+    M = orc.multipoles(pos.astype(np.float32), 1.0, K, 8, 1.0)
+    mid = (1 * K + 1) * K + 1
+    for (a, b, k), val in zip(multipole_exponents(8), M[mid]):
+        if (a + b + k) % 2:
+            assert abs(val) <= 1e-15
+        else:
+            assert val == pytest.approx(2 * np.sum(off[:, 0] ** a * off[:, 1] ** b * off[:, 2] ** k), rel=1e-12)
+
+
+def test_multipoles_monopole_and_dipole_are_mass_and_centre_of_mass(orc):
+    rng = np.random.default_rng(3)
+    K = 5
+    pos = rng.random((4000, 3)).astype(np.float32)
+    m = 0.37
+    M = orc.multipoles(pos, 1.0, K, 2, m)
+    c = np.minimum(np.floor(pos.astype(np.float64) * K), K - 1).astype(np.int64)
+    lin = (c[:, 0] * K + c[:, 1]) * K + c[:, 2]
+    counts = np.bincount(lin, minlength=K ** 3)
+    assert np.allclose(M[:, 0], m * counts, rtol=0, atol=1e-12)
+    rel = pos.astype(np.float64) * K - (c + 0.5)
+    for d in range(3):
+        assert np.allclose(M[:, 1 + d], m * np.bincount(lin, weights=rel[:, d], minlength=K ** 3), atol=1e-11)
+
+
+def test_multipoles_shift_theorem(orc):
+    """Moments about a displaced centre follow from the cell moments by the binomial theorem:
+    sum_j (u_j + h)^a = sum_i C(a, i) h^(a-i) M^(i).  Checked for the x-exponent of every component."""
+    from math import comb
+    from oracle import multipole_exponents
+    rng = np.random.default_rng(4)
+    K = 2
+    pos = (rng.random((300, 3)) * 0.5).astype(np.float32)        # all in cell (0, 0, 0)
+    M = orc.multipoles(pos, 1.0, K, 8, 1.0)[0]
+    idx = {e: i for i, e in enumerate(multipole_exponents(8))}
+    rel = pos.astype(np.float64) * K - 0.5
+    h = 0.3
+    for (a, b, k) in multipole_exponents(8):
+        direct = np.sum((rel[:, 0] + h) ** a * rel[:, 1] ** b * rel[:, 2] ** k)
+        shifted = sum(comb(a, i) * h ** (a - i) * M[idx[(i, b, k)]] for i in range(a + 1))
+        assert shifted == pytest.approx(direct, rel=1e-10, abs=1e-12)
