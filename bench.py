@@ -33,10 +33,9 @@ def log(msg):
 
 
 def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2110_11398_amd", "csrc"))):
-        h.update(open(os.path.join(ROOT, "paper_2110_11398_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+    """Digest of the force kernel's source file (a counter summary is valid only for these sources)."""
+    return hashlib.sha256(open(os.path.join(ROOT, "paper_2110_11398_amd", "csrc", "forces.hip"), "rb").read()
+                          ).hexdigest()[:16]
 
 
 def traffic_from_profile(workload: str, kind: str, mode: str, tuning: dict):
@@ -106,6 +105,9 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="capture one step (build_cells + forces) in a HIP graph and time its replays")
     ap.add_argument("--tuning", default="", help="comma list k=v of abacus_nf_tuning fields")
+    ap.add_argument("--stage", default="forces", choices=["forces", "multipoles"],
+                    help="forces: the near-field step (default); multipoles: cell multipoles of the layout")
+    ap.add_argument("--order", type=int, default=8, help="multipole order for --stage multipoles")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -138,6 +140,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
+    if args.stage == "multipoles":
+        print(json.dumps(run_multipoles(args, nf, torch, w, pos, boxes)), flush=True)
+        return
     threads = min(16, os.cpu_count() or 1)
     samples = {}
     for kname in args.kind.split(","):
@@ -234,6 +239,37 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
            "roofline": roofline}
     cells.free()
     return out
+
+
+def run_multipoles(args, nf, torch, w, pos, boxes):
+    """Cell multipoles of order p from the built layout; HBM-bound, so the roofline is bytes/s."""
+    cells = nf.build_cells(pos, boxes, 2)
+    n, nc = cells.size()
+    p = args.order
+    ncomp = (p + 1) * (p + 2) * (p + 3) // 6
+    mass = [b.gm for b in w.boxes]
+    out = torch.empty((nc, ncomp), dtype=torch.float64, device="cuda")
+    for _ in range(max(1, args.warmup)):
+        cells.multipoles(p, mass, out)
+    nf.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        cells.multipoles(p, mass, out)
+    e1.record()
+    torch.cuda.synchronize()
+    nf.sync()
+    ms = e0.elapsed_time(e1) / args.steps
+    nbytes = 16 * n + 4 * (nc + 1) + 8 * ncomp * nc   # spos read once, cell offsets, moments written once
+    cells.free()
+    return {"metric": "cell multipoles: particles/s", "value": n / (ms / 1e3), "unit": "particles/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{args.workload}: {w.description}", "n": n, "cells": nc, "order": p,
+                       "components": ncomp},
+            "roofline": {"bound": "hbm", "achieved": nbytes / (ms / 1e3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": nbytes / (ms / 1e3) / 1e9 / 8000.0, "traffic": None, "kernel": "k_multipoles",
+                         "kernel_ms": ms, "bytes_per_launch": nbytes}}
 
 
 if __name__ == "__main__":

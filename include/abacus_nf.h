@@ -149,6 +149,25 @@ int abacus_nf_forces_density(abacus_nf_cells cells, const double *eps, abacus_nf
                              abacus_nf_sum mode, const double *b, float *acc, float *rho, void *hip_stream);
 
 /*
+ * abacus_nf_multipoles -- multipole moments of the mass in every cell (Sec. 3.1:
+ * the far-field Taylor coefficients are built from the cells' multipole moments;
+ * AbacusSummit uses order p = 8), computed from the handle's cell-relative
+ * coordinates:
+ *     M_c^(a,b,k) = m * sum_{j in c} u_j^a v_j^b w_j^k,   a + b + k <= order,
+ * (u, v, w) = position relative to the centre of its cell in cell widths (the
+ * complete Cartesian basis; a reading, since the paper does not print its basis).
+ *
+ *   order  0 <= order <= 10; components per cell (order+1)(order+2)(order+3)/6
+ *          (165 for order 8), ordered by degree n = 0..order, then a = n..0,
+ *          then b = n-a..0 (k = n-a-b).
+ *   mass   host double [n_boxes]: particle mass m of each box.
+ *   out    device float64 [n_cells][components], cells in global order (box by
+ *          box, (cx*K + cy)*K + cz within a box); every cell is written.
+ * Sums are FP64 in slot order (deterministic).  Allocates nothing.
+ */
+int abacus_nf_multipoles(abacus_nf_cells cells, int32_t order, const double *mass, double *out, void *hip_stream);
+
+/*
  * abacus_nf_sync -- wait for the stream, then return (and clear) the first
  * error recorded on the current device since the last sync: ENONFINITE,
  * ECAPACITY, or EDEVICE if the stream itself failed.

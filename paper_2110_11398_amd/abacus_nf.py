@@ -65,6 +65,7 @@ def library():
         "abacus_nf_forces": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int, vp, vp],
         "abacus_nf_forces_density": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int,
                                      ctypes.POINTER(d), vp, vp, vp],
+        "abacus_nf_multipoles": [vp, i32, ctypes.POINTER(d), vp, vp],
         "abacus_nf_sync": [vp],
         "abacus_nf_free_cells": [vp],
         "abacus_nf_interactions": [vp, vp, ctypes.POINTER(i64)],
@@ -79,6 +80,8 @@ def library():
         "abacus_nf_version": [],
     }
     for name, args in sig.items():
+        if not hasattr(lib, name):   # an older build of the library (see ABACUS_NF_LIBRARY)
+            continue
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
@@ -178,6 +181,23 @@ class Cells:
                                                 ctypes.c_void_p(_stream_handle(stream)))
         _check(rc, "abacus_nf_forces_density")
         return out, rho
+
+    def multipoles(self, order: int = 8, mass: Optional[Sequence[float]] = None, out=None, stream=None):
+        """abacus_nf_multipoles: [n_cells, (order+1)(order+2)(order+3)/6] float64 device tensor."""
+        import torch
+        n, nc = self.size()
+        ncomp = (order + 1) * (order + 2) * (order + 3) // 6
+        if mass is None:
+            mass = [1.0] * len(self.boxes)
+        if out is None:
+            out = torch.empty((nc, ncomp), dtype=torch.float64, device="cuda")
+        if not (out.is_cuda and out.dtype == torch.float64 and out.shape == (nc, ncomp) and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 [n_cells, components] GPU tensor")
+        rc = library().abacus_nf_multipoles(self._h, int(order), _doubles(mass),
+                                            ctypes.c_void_p(out.data_ptr() if out.numel() else None),
+                                            ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_multipoles")
+        return out
 
     def interactions(self, stream=None) -> int:
         v = ctypes.c_int64(0)

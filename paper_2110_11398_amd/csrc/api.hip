@@ -32,6 +32,7 @@ struct abacus_nf_cells_s {
     void *radix_temp = nullptr;
     void *scan_temp = nullptr;
     BoxDev *d_boxes = nullptr;
+    double *d_mass = nullptr;  // per-box mass for the multipoles
 
     // force work buffers
     int64_t wcap_cells = -1, wcap_items = -1, wcap_partials = -1, wcap_boxes = -1;
@@ -91,7 +92,7 @@ bool dalloc_bytes(void *&p, size_t bytes) {
 
 void free_sort_buffers(abacus_nf_cells_s *h) {
     dfree(h->keys_a); dfree(h->vals_a); dfree(h->keys_b); dfree(h->vals_b);
-    dfree(h->spos); dfree(h->cell_start); dfree(h->endpos); dfree(h->d_boxes);
+    dfree(h->spos); dfree(h->cell_start); dfree(h->endpos); dfree(h->d_boxes); dfree(h->d_mass);
     if (h->radix_temp) hipFree(h->radix_temp);
     if (h->scan_temp) hipFree(h->scan_temp);
     h->radix_temp = h->scan_temp = nullptr;
@@ -254,7 +255,7 @@ int abacus_nf_build_cells(const float *pos, int64_t n_total, const abacus_nf_box
         const int64_t cn = std::max<int64_t>(n, 1), cc = std::max<int64_t>(cells_total, 1);
         bool ok = dalloc(h->keys_a, cn) && dalloc(h->vals_a, cn) && dalloc(h->keys_b, cn) &&
                   dalloc(h->vals_b, cn) && dalloc(h->spos, cn) && dalloc(h->cell_start, cc + 1) &&
-                  dalloc(h->endpos, cc) && dalloc(h->d_boxes, n_boxes) &&
+                  dalloc(h->endpos, cc) && dalloc(h->d_boxes, n_boxes) && dalloc(h->d_mass, n_boxes) &&
                   dalloc_bytes(h->radix_temp, radix_temp_bytes(cn)) &&
                   dalloc_bytes(h->scan_temp, scan_temp_bytes(std::max(cc, cn)));
         if (!ok) {
@@ -420,6 +421,21 @@ int abacus_nf_forces_density(abacus_nf_cells h, const double *eps, abacus_nf_kin
                              abacus_nf_sum mode, const double *b, float *acc, float *rho, void *hip_stream) {
     if (!b) return ABACUS_NF_EINVAL;
     return forces_impl(h, eps, kind, gm, mode, b, acc, rho, hip_stream);
+}
+
+int abacus_nf_multipoles(abacus_nf_cells h, int32_t order, const double *mass, double *out, void *hip_stream) {
+    if (!h || !mass) return ABACUS_NF_EINVAL;
+    if (order < 0 || order > multipole_max_order()) return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    if (h->n_cells > 0 && !out) return ABACUS_NF_EINVAL;
+    for (int b = 0; b < h->n_boxes; b++)
+        if (!std::isfinite(mass[b])) return ABACUS_NF_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (dev != h->device) return ABACUS_NF_ESTATE;
+    hipError_t e = launch_multipoles(h->spos, h->cell_start, h->d_boxes, h->n_boxes, h->n_cells, order, mass,
+                                     h->d_mass, out, dev, (hipStream_t)hip_stream);
+    return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 
 int abacus_nf_sync(void *hip_stream) {

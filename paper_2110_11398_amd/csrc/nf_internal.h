@@ -121,6 +121,13 @@ hipError_t launch_gather(const float *pos, const int32_t *perm, const int32_t *k
                          const BoxDev *boxes, int n_boxes, float4 *spos, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 
+// Cell multipoles (multipoles.hip)
+int multipole_components(int p);
+int multipole_max_order();
+hipError_t launch_multipoles(const float4 *spos, const int32_t *cs, const BoxDev *boxes, int n_boxes,
+                             int64_t n_cells, int p, const double *mass_host, double *mass_dev, double *out,
+                             int device, hipStream_t st);
+
 // Work list and forces (forces.hip)
 struct ForcesArgs {
     const float4 *spos;

@@ -488,3 +488,61 @@ def test_density_rejects_bad_radius(nf):
     with pytest.raises(nf.NearFieldError):
         c.forces_density([0.01], [1.0], [1e-9])
     c.free()
+
+
+# ---------------------------------------------------------------- cell multipoles (Sec. 3.1)
+
+def _mp_check(got, ref, counts, m, what):
+    """|M_gpu - M_ref| <= 2^-22 m n_c per component: positions enter as FP32 cell-relative coordinates
+    (rounded once, <= 2^-26 cell widths), and every monomial has |value| <= 1 with degree <= 10."""
+    tol = 2.0 ** -22 * abs(m) * np.maximum(counts, 1)[:, None]
+    err = np.abs(got - ref)
+    print(f"{what}: cells={got.shape[0]} comps={got.shape[1]} max err/tol {np.max(err / tol):.3e}", flush=True)
+    assert np.all(err <= tol), what
+
+
+@pytest.mark.parametrize("order", [0, 1, 8, 10])
+def test_multipoles_tiny(nf, tiny, order):
+    b, _ = tiny
+    pos = torch.from_numpy(b.pos).cuda()
+    c = nf.build_cells(pos, [(b.n, b.box, b.K)], 2)
+    got = c.multipoles(order, [0.5]).cpu().numpy()
+    nf.sync()
+    ref = oracle.multipoles(b.pos, b.box, b.K, order, 0.5)
+    counts = np.bincount(oracle.bin_cells(b.pos, b.box, b.K), minlength=b.K ** 3)
+    _mp_check(got, ref, counts, 0.5, f"multipoles tiny order={order}")
+    c.free()
+
+
+def test_multipoles_clustered_and_batched(nf):
+    w = gen.workload("batched", n_boxes=5, lo=20 ** 3, hi=40 ** 3)
+    pos = torch.from_numpy(w.concat_positions()).cuda()
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    masses = [1.0 / b.n for b in w.boxes]
+    c = nf.build_cells(pos, boxes, 2)
+    got = c.multipoles(8, masses).cpu().numpy()
+    nf.sync()
+    base = 0
+    for b, m in zip(w.boxes, masses):
+        nc = b.K ** 3
+        ref = oracle.multipoles(b.pos, b.box, b.K, 8, m)
+        counts = np.bincount(oracle.bin_cells(b.pos, b.box, b.K), minlength=nc)
+        _mp_check(got[base:base + nc], ref, counts, m, f"multipoles box n={b.n} K={b.K}")
+        base += nc
+    c.free()
+
+
+def test_multipoles_heavy_cell_and_empty_cells(nf):
+    rng = np.random.default_rng(5)
+    p = np.concatenate([0.5 + 0.01 * rng.standard_normal((30000, 3)), rng.random((100, 3))]) % 1.0
+    p = p.astype(np.float32)
+    c = nf.build_cells(torch.from_numpy(p).cuda(), [(len(p), 1.0, 12)], 2)
+    got = c.multipoles(8, [2.0]).cpu().numpy()
+    nf.sync()
+    ref = oracle.multipoles(p, 1.0, 12, 8, 2.0)
+    counts = np.bincount(oracle.bin_cells(p, 1.0, 12), minlength=12 ** 3)
+    assert np.all(got[counts == 0] == 0.0)
+    _mp_check(got, ref, counts, 2.0, "multipoles heavy")
+    with pytest.raises(nf.NearFieldError):
+        c.multipoles(11)
+    c.free()
