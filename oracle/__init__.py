@@ -11,6 +11,8 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   max(0, 1 - r^2/b^2) over the near field, self pair included (a reading).
 * cell multipoles (Sec. 3.1, order p = 8): complete Cartesian moments about
   each cell centre, positions in cell widths (a reading of the basis).
+* far field from per-cell Taylor series (Sec. 3.1): -grad of the series about
+  each cell centre, co-added to a force array.
 * ``brute.py``: an independent NumPy all-pairs x 27-image enumeration for tiny
   inputs, which keeps a pair exactly when its cell offset lies in [-R, R]^3.
 
@@ -19,9 +21,11 @@ is pinned to the reading (value, slope and curvature matching 1/r^2 at r=eps)
 but "parity unpinned" against the original code.
 """
 from .oracle import (lib_path, build, compile_oracle, Oracle, default, bin_cells, kernel_g,
-                     forces, count_pairs, density, multipoles, multipole_exponents, forces_boxes, SOURCE,
+                     forces, count_pairs, density, multipoles, multipole_exponents, taylor_forces, forces_boxes,
+                     SOURCE,
                      SPLINE, PLUMMER)
 
 __all__ = ["lib_path", "build", "compile_oracle", "Oracle", "default", "bin_cells", "kernel_g",
-           "forces", "count_pairs", "density", "multipoles", "multipole_exponents", "forces_boxes", "SOURCE",
+           "forces", "count_pairs", "density", "multipoles", "multipole_exponents", "taylor_forces",
+           "forces_boxes", "SOURCE",
            "SPLINE", "PLUMMER"]

@@ -60,8 +60,9 @@ class Oracle:
         lib.oracle_nf_count_pairs.argtypes = [vp, c_i64, c_d, ci, ci, vp]
         lib.oracle_nf_density.argtypes = [vp, c_i64, c_d, ci, ci, c_d, vp, c_i64, ci, vp]
         lib.oracle_nf_multipoles.argtypes = [vp, c_i64, c_d, ci, ci, c_d, vp]
+        lib.oracle_nf_taylor.argtypes = [vp, c_i64, c_d, ci, ci, vp, vp]
         for f in (lib.oracle_nf_bin, lib.oracle_nf_kernel, lib.oracle_nf_forces, lib.oracle_nf_count_pairs,
-                  lib.oracle_nf_density, lib.oracle_nf_multipoles):
+                  lib.oracle_nf_density, lib.oracle_nf_multipoles, lib.oracle_nf_taylor):
             f.restype = ctypes.c_int
         self.lib = lib
         self.path = path
@@ -132,6 +133,16 @@ class Oracle:
                                              int(p), float(m), out.ctypes.data), "multipoles")
         return out
 
+    def taylor_forces(self, pos, box: float, K: int, p: int, taylor, acc=None) -> np.ndarray:
+        """acc + far-field acceleration -grad Phi of the cell Taylor series (FP64 [n, 3])."""
+        q = _pos32(pos)
+        n = q.shape[0]
+        T = np.ascontiguousarray(taylor, dtype=np.float64)
+        out = np.zeros((n, 3)) if acc is None else np.array(acc, dtype=np.float64, copy=True)
+        _check(self.lib.oracle_nf_taylor(q.ctypes.data if n else None, n, float(box), int(K), int(p), T.ctypes.data,
+                                         out.ctypes.data if n else None), "taylor")
+        return out
+
     def count_pairs(self, pos, box: float, K: int, R: int = 2) -> int:
         """Exact number of (sink, source) pairs, self pairs included, from cell occupancy."""
         p = _pos32(pos)
@@ -176,6 +187,10 @@ def density(pos, box, K, R, b, sinks=None, threads=0):
 
 def multipoles(pos, box, K, p=8, m=1.0):
     return default().multipoles(pos, box, K, p, m)
+
+
+def taylor_forces(pos, box, K, p, taylor, acc=None):
+    return default().taylor_forces(pos, box, K, p, taylor, acc)
 
 
 def multipole_exponents(p: int):

@@ -44,6 +44,10 @@
  * of the mass in each cell, order p = 8): complete Cartesian moments about the
  * cell centre in cell widths (see oracle_nf_multipoles).
  *
+ * Far field from per-cell Taylor series (Sec. 3.1): the gradient of
+ * Phi = sum T^(a,b,k) u^a v^b w^k about each cell centre, added to a force
+ * array (see oracle_nf_taylor).
+ *
  * Coincident particles (including the self pair) contribute exactly zero force.
  * Sums are plain FP64 in a fixed order (neighbour cells in lexicographic
  * (dx,dy,dz) order, sources in input order within a cell), or Neumaier
@@ -362,6 +366,53 @@ int oracle_nf_multipoles(const float *pos, int64_t n, double L, int K, int p, do
                     const int k = deg - a - b;
                     o[idx++] += m * (pu[a] * pv[b] * pw[k]);
                 }
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * Far-field force from per-cell Taylor series, co-added to the near field
+ * (Sec. 3.1: the far-field acceleration is a Taylor expansion of the potential
+ * about each cell centre, order p; singlestep evaluates its gradient at every
+ * particle and adds it to the near-field force).  With (u, v, w) the
+ * particle's position relative to its cell centre in cell widths and
+ *     Phi(u, v, w) = sum_{a+b+k <= p} T^(a,b,k) u^a v^b w^k
+ * (coefficients in the component order of oracle_nf_multipoles), the far-field
+ * acceleration in box units is -grad_x Phi = -(K/L) grad_u Phi:
+ *     a_x = -(K/L) sum a T^(a,b,k) u^(a-1) v^b w^k, and likewise for y, z.
+ *   taylor [K^3][ncomp] float64;  acc [n][3] float64 in/out (the far field is added).
+ */
+int oracle_nf_taylor(const float *pos, int64_t n, double L, int K, int p, const double *taylor, double *acc) {
+    if (n < 0 || !(L > 0) || K < 1 || p < 0 || p > 16 || (n > 0 && (!pos || !taylor || !acc))) return ORACLE_EINVAL;
+    const int ncomp = (p + 1) * (p + 2) * (p + 3) / 6;
+    const double s = (double)K / L;
+    for (int64_t i = 0; i < n; i++) {
+        double t[3];
+        int c[3];
+        for (int d = 0; d < 3; d++) {
+            double xt;
+            c[d] = axis_cell((double)pos[3 * i + d], L, s, K, &xt);
+            t[d] = xt * s - ((double)c[d] + 0.5);
+        }
+        double pw3[3][17];
+        for (int d = 0; d < 3; d++) {
+            pw3[d][0] = 1.0;
+            for (int q = 1; q <= p; q++) pw3[d][q] = pw3[d][q - 1] * t[d];
+        }
+        const double *T = taylor + (((int64_t)c[0] * K + c[1]) * K + c[2]) * ncomp;
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        int idx = 0;
+        for (int deg = 0; deg <= p; deg++)
+            for (int a = deg; a >= 0; a--)
+                for (int b = deg - a; b >= 0; b--, idx++) {
+                    const int k = deg - a - b;
+                    if (a > 0) gx += T[idx] * a * pw3[0][a - 1] * pw3[1][b] * pw3[2][k];
+                    if (b > 0) gy += T[idx] * b * pw3[0][a] * pw3[1][b - 1] * pw3[2][k];
+                    if (k > 0) gz += T[idx] * k * pw3[0][a] * pw3[1][b] * pw3[2][k - 1];
+                }
+        acc[3 * i + 0] -= s * gx;
+        acc[3 * i + 1] -= s * gy;
+        acc[3 * i + 2] -= s * gz;
     }
     return ORACLE_OK;
 }

@@ -27,6 +27,10 @@ MUTANTS = {
     "multipole_centre": ("t[d] = xt * s - ((double)c[d] + 0.5);", "t[d] = xt * s - (double)c[d];"),
     "multipole_power": ("pw[q] = pw[q - 1] * t[2];", "pw[q] = pw[q - 1] * t[1];"),
     "multipole_order": ("for (int b = deg - a; b >= 0; b--) {", "for (int b = 0; b <= deg - a; b++) {"),
+    "taylor_sign": ("acc[3 * i + 1] -= s * gy;", "acc[3 * i + 1] += s * gy;"),
+    "taylor_scale": ("acc[3 * i + 0] -= s * gx;", "acc[3 * i + 0] -= gx;"),
+    "taylor_derivative": ("if (k > 0) gz += T[idx] * k * pw3[0][a] * pw3[1][b] * pw3[2][k - 1];",
+                          "if (k > 0) gz += T[idx] * pw3[0][a] * pw3[1][b] * pw3[2][k - 1];"),
     "density_self_excluded": ("if (w > 0.0) sum += w;", "if (w > 0.0 && w < 1.0) sum += w;"),
     "density_image_dropped": ("double ddz = (xt[3 * j + 2] + sz * L) - zi;\n                        double w",
                               "double ddz = xt[3 * j + 2] - zi;\n                        double w"),
@@ -68,6 +72,14 @@ def battery(o: oracle.Oracle) -> list:
     M = o.multipoles(q, 1.0, 4, 8, 1.0)[(2 * 4 + 1) * 4 + 0]
     if not np.array_equal(M, [0.25 ** a * (-0.375) ** b * 0.125 ** k for a, b, k in multipole_exponents(8)]):
         bad.append("multipoles")
+    e = multipole_exponents(8)
+    T = np.zeros((4 ** 3, len(e)))
+    T[:, e.index((1, 0, 0))] = 1.0
+    T[:, e.index((0, 1, 0))] = 2.0
+    T[:, e.index((0, 0, 3))] = 1.0
+    pts = np.array([[0.3, 0.55, 0.8125]], np.float32)                  # w = (0.8125*4 - 3.5) = -0.25
+    if not np.allclose(o.taylor_forces(pts, 1.0, 4, 8, T), [[-4.0, -8.0, -4.0 * 3 * 0.0625]], rtol=1e-12):
+        bad.append("taylor")
     return bad
 
 

@@ -365,3 +365,50 @@ def test_multipoles_shift_theorem(orc):
         direct = np.sum((rel[:, 0] + h) ** a * rel[:, 1] ** b * rel[:, 2] ** k)
         shifted = sum(comb(a, i) * h ** (a - i) * M[idx[(i, b, k)]] for i in range(a + 1))
         assert shifted == pytest.approx(direct, rel=1e-10, abs=1e-12)
+
+
+# ---------------------------------------------------------------- far field from cell Taylor series (Sec. 3.1)
+
+def test_taylor_linear_and_quadratic_potentials(orc):
+    """Phi = g u gives a_x = -(K/L) g everywhere; Phi = h v^2 gives a_y = -(K/L) 2 h v (dyadic inputs, exact)."""
+    from oracle import multipole_exponents
+    K, L, p = 4, 2.0, 8
+    e = multipole_exponents(p)
+    T = np.zeros((K ** 3, len(e)))
+    T[:, e.index((1, 0, 0))] = 3.0
+    T[:, e.index((0, 2, 0))] = -0.5
+    rng = np.random.default_rng(1)
+    pos = (rng.integers(0, 2 ** 12, size=(500, 3)) / 2 ** 12 * L).astype(np.float32)
+    a = orc.taylor_forces(pos, L, K, p, T)
+    x = pos.astype(np.float64) * (K / L)
+    v = x[:, 1] - (np.minimum(np.floor(x[:, 1]), K - 1) + 0.5)
+    assert np.all(a[:, 0] == -(K / L) * 3.0)
+    assert np.allclose(a[:, 1], (K / L) * 2 * 0.5 * v, rtol=0, atol=1e-15)
+    assert np.all(a[:, 2] == 0.0)
+    acc0 = rng.random((500, 3))
+    assert np.allclose(orc.taylor_forces(pos, L, K, p, T, acc0), acc0 + a, rtol=0, atol=1e-14)   # co-add
+
+
+def test_taylor_series_of_a_distant_mass_reproduces_its_force(orc):
+    """Fit the order-8 Taylor polynomial of Phi = -1/|x - x0| about one cell centre from samples (a plain
+    least-squares fit, independent of the oracle), then the oracle's gradient must match the exact force of
+    the distant mass to the truncation error of the series."""
+    from oracle import multipole_exponents
+    K, L, p = 8, 1.0, 8
+    w = L / K
+    cell = np.array([3, 4, 2])
+    centre = (cell + 0.5) * w
+    x0 = centre + np.array([0.41, -0.27, 0.33])              # ~4 cell widths away
+    e = multipole_exponents(p)
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-0.5, 0.5, size=(4000, 3))
+    phi = -1.0 / np.linalg.norm(centre + u * w - x0, axis=1)
+    A = np.stack([u[:, 0] ** a * u[:, 1] ** b * u[:, 2] ** k for a, b, k in e], axis=1)
+    coef = np.linalg.lstsq(A, phi, rcond=None)[0]
+    T = np.zeros((K ** 3, len(e)))
+    T[(cell[0] * K + cell[1]) * K + cell[2]] = coef
+    pts = centre + rng.uniform(-0.45, 0.45, size=(200, 3)) * w
+    acc = orc.taylor_forces(pts.astype(np.float32), L, K, p, T)
+    d = x0 - pts.astype(np.float32).astype(np.float64)
+    exact = d / np.linalg.norm(d, axis=1)[:, None] ** 3       # -grad(-1/r) points to the mass
+    assert np.allclose(acc, exact, rtol=1e-6, atol=1e-6 * np.abs(exact).max())
