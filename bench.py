@@ -105,9 +105,12 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="capture one step (build_cells + forces) in a HIP graph and time its replays")
     ap.add_argument("--tuning", default="", help="comma list k=v of abacus_nf_tuning fields")
-    ap.add_argument("--stage", default="forces", choices=["forces", "multipoles"],
-                    help="forces: the near-field step (default); multipoles: cell multipoles of the layout")
-    ap.add_argument("--order", type=int, default=8, help="multipole order for --stage multipoles")
+    ap.add_argument("--density", action="store_true",
+                    help="also compute the fused kernel density estimate (b = 0.4 x mean spacing per box)")
+    ap.add_argument("--stage", default="forces", choices=["forces", "multipoles", "taylor"],
+                    help="forces: the near-field step (default); multipoles: cell multipoles of the layout; "
+                         "taylor: far field of synthetic per-cell Taylor series co-added to the accelerations")
+    ap.add_argument("--order", type=int, default=8, help="series order for --stage multipoles / taylor")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -143,6 +146,9 @@ def main():
     if args.stage == "multipoles":
         print(json.dumps(run_multipoles(args, nf, torch, w, pos, boxes)), flush=True)
         return
+    if args.stage == "taylor":
+        print(json.dumps(run_taylor(args, nf, torch, gen, w, pos, boxes, acc)), flush=True)
+        return
     threads = min(16, os.cpu_count() or 1)
     samples = {}
     for kname in args.kind.split(","):
@@ -161,20 +167,28 @@ def main():
 
 def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mname):
     cells = nf.build_cells(pos, boxes, 2)
+    rho = torch.empty(w.n_total, dtype=torch.float32, device="cuda") if args.density else None
+    bk = [0.4 * b.box / b.n ** (1.0 / 3.0) if b.n else b.box / b.K for b in w.boxes]
+
+    def step_forces():
+        if rho is not None:
+            cells.forces_density(eps, gm, bk, kind, mode, acc, rho)
+        else:
+            cells.forces(eps, gm, kind, mode, acc)
     if args.tuning:
         cells.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
     elif not args.no_tune:
         t0 = time.perf_counter()
         t = cells.autotune(eps, gm, kind, mode, acc, reps=2, cache_path=args.tune_cache)
         log(f"tuning ({time.perf_counter() - t0:.1f} s): {t.as_dict()}")
-    cells.forces(eps, gm, kind, mode, acc)
+    step_forces()
     nf.sync()
     interactions = cells.interactions()
     log(f"interactions per step: {interactions:.6e}")
 
     for _ in range(args.warmup):
         nf.build_cells(pos, boxes, 2, cells=cells)
-        cells.forces(eps, gm, kind, mode, acc)
+        step_forces()
     nf.sync()
 
     graph = None
@@ -182,7 +196,7 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             nf.build_cells(pos, boxes, 2, cells=cells)
-            cells.forces(eps, gm, kind, mode, acc)
+            step_forces()
         graph.replay()
         torch.cuda.synchronize()
         nf.sync()
@@ -198,7 +212,7 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
             graph.replay()
         else:
             nf.build_cells(pos, boxes, 2, cells=cells)
-            cells.forces(eps, gm, kind, mode, acc)
+            step_forces()
             stage_ms += np.array(cells.last_times())
     e1.record()
     torch.cuda.synchronize()
@@ -210,7 +224,7 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
         stage_ms = np.zeros(4)
         for _ in range(args.steps):
             nf.build_cells(pos, boxes, 2, cells=cells)
-            cells.forces(eps, gm, kind, mode, acc)
+            step_forces()
             stage_ms += np.array(cells.last_times())
         stage_ms /= args.steps
         nf.sync()
@@ -232,7 +246,8 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {w.description}", "n": w.n_total, "boxes": len(w.boxes),
                       "K": [b.K for b in w.boxes][:4], "kind": kname, "mode": mname,
-                      "interactions_per_step": interactions, "tuning": tuning, "hip_graph": bool(args.graph)},
+                      "interactions_per_step": interactions, "tuning": tuning, "hip_graph": bool(args.graph),
+                      "density": bool(args.density)},
            "particle_updates_per_s": w.n_total / step_s,
            "stages_ms": {"build_cells": stage_ms[0], "work_list": stage_ms[1], "forces_kernel": stage_ms[2],
                          "finalize": stage_ms[3]},
@@ -241,35 +256,97 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
     return out
 
 
+def _time_calls(args, torch, nf, fn):
+    """Mean milliseconds per call of fn over args.steps calls after args.warmup, with events on the
+    current stream (the stream the library launches on)."""
+    for _ in range(max(1, args.warmup)):
+        fn()
+    nf.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    nf.sync()
+    return e0.elapsed_time(e1) / args.steps
+
+
+def _roofline(nbytes, flops, ms, kernel):
+    """The binding roof of a kernel that both streams HBM and does FP64 vector arithmetic: the one whose
+    fraction of its peak is higher (HBM 8 TB/s, FP64 vector 78.6 TFLOP/s)."""
+    gbs = nbytes / (ms / 1e3) / 1e9
+    tfs = flops / (ms / 1e3) / 1e12
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0}
+    alu = {"bound": "alu", "achieved": tfs, "peak": 78.6, "unit": "TFLOP/s", "frac": tfs / 78.6}
+    r = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
+    other = alu if r["bound"] == "hbm" else hbm
+    r.update({"traffic": None, "kernel": kernel, "kernel_ms": ms, "bytes_per_launch": nbytes,
+              "flops_per_launch": flops, "other_roof": other})
+    return r
+
+
+def taylor_flops_per_particle(p: int) -> int:
+    """FP64 flops the series evaluation does per particle (an FMA counts 2): powers of v and w, one Horner
+    pass (value and derivative, 2 FMAs per step) per column (b, k), then per column the product v^b w^k
+    (1), its FMA into d/du (2) and, where b > 0 or k > 0, the scaled-power product and FMA into d/dv or
+    d/dw (4 each); finally the three scaled subtractions (2 each)."""
+    f = 2 * p
+    for b in range(p + 1):
+        for k in range(p + 1 - b):
+            top = p - b - k
+            f += 4 * top + 3 + (4 if b > 0 else 0) + (4 if k > 0 else 0)
+    return f + 6
+
+
+def run_taylor(args, nf, torch, gen, w, pos, boxes, acc):
+    """Far field of synthetic per-cell Taylor series of order p at every particle, co-added to acc."""
+    cells = nf.build_cells(pos, boxes, 2)
+    n, nc = cells.size()
+    p = args.order
+    ncomp = (p + 1) * (p + 2) * (p + 3) // 6
+    T = torch.from_numpy(gen.taylor_coefficients(nc, p, seed=41, amp=1e-3)).cuda()
+    acc.zero_()
+    ms = _time_calls(args, torch, nf, lambda: cells.taylor_forces(p, T, acc))
+    occupied = sum(int((np.bincount(_cells_of(b), minlength=b.K ** 3) > 0).sum()) for b in w.boxes)
+    # positions and permutation read, accelerations read and written, coefficients of occupied cells read
+    nbytes = 16 * n + 4 * n + 24 * n + 4 * (nc + 1) + 8 * ncomp * occupied
+    flops = taylor_flops_per_particle(p) * n
+    cells.free()
+    return {"metric": "far-field Taylor evaluation: particles/s", "value": n / (ms / 1e3), "unit": "particles/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{args.workload}: {w.description}", "n": n, "cells": nc,
+                       "occupied_cells": occupied, "order": p, "components": ncomp},
+            "roofline": _roofline(nbytes, flops, ms, "k_taylor")}
+
+
+def _cells_of(b):
+    """Cell index of every particle of a box (floor of the position in cell widths, clamped)."""
+    t = np.minimum(np.floor(b.pos.astype(np.float64) * (b.K / b.box)).astype(np.int64), b.K - 1)
+    return (t[:, 0] * b.K + t[:, 1]) * b.K + t[:, 2]
+
+
 def run_multipoles(args, nf, torch, w, pos, boxes):
-    """Cell multipoles of order p from the built layout; HBM-bound, so the roofline is bytes/s."""
+    """Cell multipoles of order p from the built layout."""
     cells = nf.build_cells(pos, boxes, 2)
     n, nc = cells.size()
     p = args.order
     ncomp = (p + 1) * (p + 2) * (p + 3) // 6
     mass = [b.gm for b in w.boxes]
     out = torch.empty((nc, ncomp), dtype=torch.float64, device="cuda")
-    for _ in range(max(1, args.warmup)):
-        cells.multipoles(p, mass, out)
-    nf.sync()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        cells.multipoles(p, mass, out)
-    e1.record()
-    torch.cuda.synchronize()
-    nf.sync()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = _time_calls(args, torch, nf, lambda: cells.multipoles(p, mass, out))
     nbytes = 16 * n + 4 * (nc + 1) + 8 * ncomp * nc   # spos read once, cell offsets, moments written once
+    # per particle: 3p powers, then per component two products and an add
+    flops = (3 * p + 3 * ncomp) * n
     cells.free()
     return {"metric": "cell multipoles: particles/s", "value": n / (ms / 1e3), "unit": "particles/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"{args.workload}: {w.description}", "n": n, "cells": nc, "order": p,
                        "components": ncomp},
-            "roofline": {"bound": "hbm", "achieved": nbytes / (ms / 1e3) / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": nbytes / (ms / 1e3) / 1e9 / 8000.0, "traffic": None, "kernel": "k_multipoles",
-                         "kernel_ms": ms, "bytes_per_launch": nbytes}}
+            "roofline": _roofline(nbytes, flops, ms,
+                                  "abacus_nf_multipoles call (k_mp_units, scans, k_multipoles, k_mp_combine)")}
 
 
 if __name__ == "__main__":

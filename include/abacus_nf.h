@@ -163,9 +163,30 @@ int abacus_nf_forces_density(abacus_nf_cells cells, const double *eps, abacus_nf
  *   mass   host double [n_boxes]: particle mass m of each box.
  *   out    device float64 [n_cells][components], cells in global order (box by
  *          box, (cx*K + cy)*K + cz within a box); every cell is written.
- * Sums are FP64 in slot order (deterministic).  Allocates nothing.
+ * Sums are FP64 in a fixed order (deterministic): cells with more than 2048
+ * particles are cut into units of 2048 whose partial moments are added in order.
+ * The first call on a handle (or one with a higher order or a larger batch)
+ * allocates the unit bookkeeping; later calls allocate nothing.
  */
 int abacus_nf_multipoles(abacus_nf_cells cells, int32_t order, const double *mass, double *out, void *hip_stream);
+
+/*
+ * abacus_nf_taylor_forces -- add the far-field acceleration of per-cell Taylor
+ * series to acc (Sec. 3.1: the far field is a Taylor expansion of the potential
+ * about each cell centre, order p; its gradient at each particle is co-added to
+ * the near-field force).  With (u, v, w) the position relative to the centre of
+ * its cell in cell widths and Phi = sum T^(a,b,k) u^a v^b w^k over a+b+k <= order,
+ *     acc_i += -(K/L) grad_(u,v,w) Phi   (evaluated in FP64, acc rounded to FP32).
+ *
+ *   order   0 <= order <= 10.
+ *   taylor  device float64 [n_cells][components], the coefficients of every cell
+ *           in the component order of abacus_nf_multipoles (cells in global order).
+ *   acc     device float32 [n_total][3], input order, read and written (typically
+ *           the output of abacus_nf_forces on the same stream).
+ * Allocates nothing.
+ */
+int abacus_nf_taylor_forces(abacus_nf_cells cells, int32_t order, const double *taylor, float *acc,
+                            void *hip_stream);
 
 /*
  * abacus_nf_sync -- wait for the stream, then return (and clear) the first

@@ -66,6 +66,7 @@ def library():
         "abacus_nf_forces_density": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int,
                                      ctypes.POINTER(d), vp, vp, vp],
         "abacus_nf_multipoles": [vp, i32, ctypes.POINTER(d), vp, vp],
+        "abacus_nf_taylor_forces": [vp, i32, vp, vp, vp],
         "abacus_nf_sync": [vp],
         "abacus_nf_free_cells": [vp],
         "abacus_nf_interactions": [vp, vp, ctypes.POINTER(i64)],
@@ -198,6 +199,23 @@ class Cells:
                                             ctypes.c_void_p(_stream_handle(stream)))
         _check(rc, "abacus_nf_multipoles")
         return out
+
+    def taylor_forces(self, order: int, taylor, acc, stream=None):
+        """abacus_nf_taylor_forces: acc (float32 [N,3] device) += far field of the cell Taylor series
+        taylor (float64 [n_cells, components] device)."""
+        import torch
+        n, nc = self.size()
+        ncomp = (order + 1) * (order + 2) * (order + 3) // 6
+        if not (taylor.is_cuda and taylor.dtype == torch.float64 and taylor.shape == (nc, ncomp)
+                and taylor.is_contiguous()):
+            raise ValueError("taylor must be a contiguous float64 [n_cells, components] GPU tensor")
+        if not (acc.is_cuda and acc.dtype == torch.float32 and acc.shape == (n, 3) and acc.is_contiguous()):
+            raise ValueError("acc must be a contiguous float32 [N,3] GPU tensor")
+        rc = library().abacus_nf_taylor_forces(self._h, int(order), ctypes.c_void_p(taylor.data_ptr() or None),
+                                               ctypes.c_void_p(acc.data_ptr() or None),
+                                               ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_taylor_forces")
+        return acc
 
     def interactions(self, stream=None) -> int:
         v = ctypes.c_int64(0)

@@ -33,6 +33,13 @@ struct abacus_nf_cells_s {
     void *scan_temp = nullptr;
     BoxDev *d_boxes = nullptr;
     double *d_mass = nullptr;  // per-box mass for the multipoles
+    // multipole work units (allocated by the first multipoles call of a batch shape)
+    int64_t mcap_cells = -1, mcap_slots = -1;
+    int mcap_comp = -1;
+    int64_t *mp_unit_cnt = nullptr, *mp_heavy_cnt = nullptr, *mp_unit_base = nullptr, *mp_heavy_base = nullptr;
+    int32_t *mp_heavy_list = nullptr, *mp_heavy_n = nullptr;
+    double *mp_partials = nullptr;
+    void *mp_scan_temp = nullptr;
 
     // force work buffers
     int64_t wcap_cells = -1, wcap_items = -1, wcap_partials = -1, wcap_boxes = -1;
@@ -111,6 +118,15 @@ void mark(abacus_nf_cells_s *h, int stage, bool end, hipStream_t st) {
     if (!h->timing || !h->ev[2 * stage + (end ? 1 : 0)]) return;
     hipEventRecord(h->ev[2 * stage + (end ? 1 : 0)], st);
     if (end) h->ev_used[stage] = true;
+}
+
+void free_mp_buffers(abacus_nf_cells_s *h) {
+    dfree(h->mp_unit_cnt); dfree(h->mp_heavy_cnt); dfree(h->mp_unit_base); dfree(h->mp_heavy_base);
+    dfree(h->mp_heavy_list); dfree(h->mp_heavy_n); dfree(h->mp_partials);
+    if (h->mp_scan_temp) hipFree(h->mp_scan_temp);
+    h->mp_scan_temp = nullptr;
+    h->mcap_cells = h->mcap_slots = -1;
+    h->mcap_comp = -1;
 }
 
 void free_work_buffers(abacus_nf_cells_s *h) {
@@ -433,8 +449,48 @@ int abacus_nf_multipoles(abacus_nf_cells h, int32_t order, const double *mass, d
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
     if (dev != h->device) return ABACUS_NF_ESTATE;
-    hipError_t e = launch_multipoles(h->spos, h->cell_start, h->d_boxes, h->n_boxes, h->n_cells, order, mass,
-                                     h->d_mass, out, dev, (hipStream_t)hip_stream);
+    const int64_t nc = std::max<int64_t>(h->n_cells, 1);
+    const int64_t slots = (int64_t)multipole_scratch_slots(h->n_total, h->n_cells);
+    const int comp = multipole_components(order);
+    if (h->mcap_cells < nc || h->mcap_slots < slots || h->mcap_comp < comp) {
+        free_mp_buffers(h);
+        bool ok = dalloc(h->mp_unit_cnt, nc) && dalloc(h->mp_heavy_cnt, nc) && dalloc(h->mp_unit_base, nc) &&
+                  dalloc(h->mp_heavy_base, nc) && dalloc(h->mp_heavy_list, slots) && dalloc(h->mp_heavy_n, 1) &&
+                  dalloc(h->mp_partials, (size_t)slots * comp) &&
+                  dalloc_bytes(h->mp_scan_temp, scan_temp_bytes(nc));
+        if (!ok) {
+            free_mp_buffers(h);
+            return ABACUS_NF_ENOMEM;
+        }
+        h->mcap_cells = nc;
+        h->mcap_slots = slots;
+        h->mcap_comp = comp;
+    }
+    MultipoleBuffers mb;
+    mb.mass = h->d_mass;
+    mb.unit_cnt = h->mp_unit_cnt;
+    mb.heavy_cnt = h->mp_heavy_cnt;
+    mb.unit_base = h->mp_unit_base;
+    mb.heavy_base = h->mp_heavy_base;
+    mb.heavy_list = h->mp_heavy_list;
+    mb.heavy_n = h->mp_heavy_n;
+    mb.partials = h->mp_partials;
+    hipError_t e = launch_multipoles(mb, h->spos, h->cell_start, h->d_boxes, h->n_boxes, h->n_cells, order, mass,
+                                     out, dev, h->mp_scan_temp, (hipStream_t)hip_stream);
+    return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
+}
+
+int abacus_nf_taylor_forces(abacus_nf_cells h, int32_t order, const double *taylor, float *acc, void *hip_stream) {
+    if (!h) return ABACUS_NF_EINVAL;
+    if (order < 0 || order > taylor_max_order()) return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    if (h->n_total > 0 && (!taylor || !acc)) return ABACUS_NF_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (dev != h->device) return ABACUS_NF_ESTATE;
+    if (h->n_total == 0) return ABACUS_NF_OK;
+    hipError_t e = launch_taylor(h->spos, h->cell_start, h->perm, h->d_boxes, h->n_boxes, h->n_cells, order, taylor,
+                                 acc, dev, (hipStream_t)hip_stream);
     return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 
@@ -467,6 +523,7 @@ int abacus_nf_free_cells(abacus_nf_cells h) {
         if (hipDeviceSynchronize() != hipSuccess) rc = hip_fail(hipErrorUnknown);
         free_sort_buffers(h);
         free_work_buffers(h);
+        free_mp_buffers(h);
         destroy_events(h);
         if (cur != h->device) hipSetDevice(cur);
     }

@@ -546,3 +546,158 @@ def test_multipoles_heavy_cell_and_empty_cells(nf):
     with pytest.raises(nf.NearFieldError):
         c.multipoles(11)
     c.free()
+
+
+def _mp_cell_of(n_in_cell, K=8, seed=0):
+    """Positions with exactly n_in_cell particles inside cell (3, 4, 5) of a unit box with K cells per side, plus
+    a uniform background of K^3 particles outside it."""
+    rng = np.random.default_rng(seed)
+    w = 1.0 / K
+    inner = (np.array([3, 4, 5]) + 0.05 + 0.9 * rng.random((n_in_cell, 3))) * w
+    bg = rng.random((4 * K ** 3, 3))
+    cell = np.floor(bg / w).astype(int)
+    bg = bg[~np.all(cell == [3, 4, 5], axis=1)][:K ** 3]
+    return np.concatenate([inner, bg]).astype(np.float32)
+
+
+@pytest.mark.parametrize("n_in_cell", [2047, 2048, 2049, 4096, 6001])
+def test_multipoles_unit_boundaries_and_determinism(nf, n_in_cell):
+    """Cells are cut into units of 2048 particles: one below, at and above a unit boundary, an exact multiple
+    and a ragged last unit; two calls give bit-identical moments."""
+    K = 8
+    p = _mp_cell_of(n_in_cell, K)
+    c = nf.build_cells(torch.from_numpy(p).cuda(), [(len(p), 1.0, K)], 2)
+    got = c.multipoles(8, [0.25]).cpu().numpy()
+    again = c.multipoles(8, [0.25]).cpu().numpy()
+    nf.sync()
+    ref = oracle.multipoles(p, 1.0, K, 8, 0.25)
+    counts = np.bincount(oracle.bin_cells(p, 1.0, K), minlength=K ** 3)
+    assert counts[(3 * K + 4) * K + 5] == n_in_cell
+    _mp_check(got, ref, counts, 0.25, f"multipoles cell of {n_in_cell}")
+    assert np.array_equal(got, again)
+    c.free()
+
+
+# ---------------------------------------------------------------- far field from cell Taylor series (Sec. 3.1)
+
+def _ty_exponent_degrees(p):
+    return np.array([a + b + k for (a, b, k) in oracle.multipole_exponents(p)], dtype=np.float64)
+
+
+def _ty_check(got, ref, pos, box, K, p, T, what):
+    """|a_gpu - a_ref| <= 2^-22 |a_ref| + 2^-22 (K/L) sum_c |T_c| deg_c^2 per component: the kernel evaluates
+    the series in FP64 at the FP32 cell-relative coordinates (rounded once, <= 2^-25 cell widths, and the
+    second derivatives of the series are bounded by sum |T_c| deg_c^2 since |u|, |v|, |w| <= 1/2), and the
+    co-added result is rounded once to FP32."""
+    cells = oracle.bin_cells(pos, box, K)
+    deg = _ty_exponent_degrees(p)
+    curv = (np.abs(T) * deg ** 2).sum(axis=1)[cells] * (K / box)
+    tol = 2.0 ** -22 * np.abs(ref) + 2.0 ** -22 * curv[:, None] + 1e-30
+    err = np.abs(got - ref)
+    print(f"{what}: n={got.shape[0]} max err/tol {np.max(err / tol) if err.size else 0:.3e}", flush=True)
+    assert np.all(np.isfinite(got)), what
+    assert np.all(err <= tol), what
+
+
+@pytest.mark.parametrize("order", [1, 2, 8, 10])
+def test_taylor_tiny(nf, tiny, order):
+    b, _ = tiny
+    T = gen.taylor_coefficients(b.K ** 3, order, seed=11 + order)
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    acc = torch.zeros((b.n, 3), dtype=torch.float32, device="cuda")
+    c.taylor_forces(order, torch.from_numpy(T).cuda(), acc)
+    got = acc.cpu().numpy().astype(np.float64)
+    nf.sync()
+    ref = oracle.taylor_forces(b.pos, b.box, b.K, order, T)
+    _ty_check(got, ref, b.pos, b.box, b.K, order, T, f"taylor tiny order={order}")
+    c.free()
+
+
+def test_taylor_order_zero_leaves_acc_unchanged(nf, tiny):
+    b, _ = tiny
+    T = gen.taylor_coefficients(b.K ** 3, 0, seed=3)
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    a0 = torch.from_numpy(np.random.default_rng(1).standard_normal((b.n, 3)).astype(np.float32)).cuda()
+    acc = a0.clone()
+    c.taylor_forces(0, torch.from_numpy(T).cuda(), acc)
+    nf.sync()
+    assert torch.equal(acc, a0)
+    c.free()
+
+
+@pytest.mark.parametrize("kind", [SPLINE, PLUMMER])
+def test_taylor_co_added_to_near_field(nf, tiny, kind):
+    """Near field then far field into the same acceleration array: the total matches the oracle's near field
+    plus its Taylor far field."""
+    b, tref = tiny
+    p = 8
+    T = gen.taylor_coefficients(b.K ** 3, p, seed=21, amp=1e-3)
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    acc = c.forces([b.eps], [b.gm], kind, 1)
+    near = acc.cpu().numpy().astype(np.float64)
+    c.taylor_forces(p, torch.from_numpy(T).cuda(), acc)
+    got = acc.cpu().numpy().astype(np.float64)
+    nf.sync()
+    ref_near, _, mag = tref[kind]
+    ref = oracle.taylor_forces(b.pos, b.box, b.K, p, T, ref_near)
+    # the far field is checked against the near field the kernel itself produced, so that the near-field
+    # tolerance (tested elsewhere) does not mask it ...
+    ref_from_near = oracle.taylor_forces(b.pos, b.box, b.K, p, T, near)
+    _ty_check(got, ref_from_near, b.pos, b.box, b.K, p, T, f"taylor co-add kind={kind}")
+    # ... and the total against the oracle's near + far
+    check(got, ref, mag + np.linalg.norm(ref - ref_near, axis=1), f"near+far kind={kind}")
+    c.free()
+
+
+def test_taylor_batched_boxes_and_heavy_cells(nf):
+    w = gen.workload("batched", n_boxes=5, lo=20 ** 3, hi=40 ** 3)
+    pos = torch.from_numpy(w.concat_positions()).cuda()
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    p = 8
+    nct = sum(b.K ** 3 for b in w.boxes)
+    T = gen.taylor_coefficients(nct, p, seed=31)
+    c = nf.build_cells(pos, boxes, 2)
+    a0 = np.random.default_rng(2).standard_normal((sum(b.n for b in w.boxes), 3)).astype(np.float32)
+    acc = torch.from_numpy(a0).cuda()
+    c.taylor_forces(p, torch.from_numpy(T).cuda(), acc)
+    got = acc.cpu().numpy().astype(np.float64)
+    nf.sync()
+    off, cb = 0, 0
+    for b in w.boxes:
+        nc = b.K ** 3
+        Tb = T[cb:cb + nc]
+        ref = oracle.taylor_forces(b.pos, b.box, b.K, p, Tb, a0[off:off + b.n])
+        _ty_check(got[off:off + b.n], ref, b.pos, b.box, b.K, p, Tb, f"taylor box n={b.n} K={b.K}")
+        off += b.n
+        cb += nc
+    c.free()
+
+
+def test_taylor_clustered_full_size_sampled(nf):
+    """The clustered workload at full size, the series of order 8 in every cell; checked on 20000 sampled
+    particles (each particle's far field depends only on its own position and cell)."""
+    w = gen.workload("clustered")
+    b = w.boxes[0]
+    p = 8
+    T = gen.taylor_coefficients(b.K ** 3, p, seed=41, amp=1e-3)
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    acc = torch.zeros((b.n, 3), dtype=torch.float32, device="cuda")
+    c.taylor_forces(p, torch.from_numpy(T).cuda(), acc)
+    idx = gen.sample_sinks(b.n, 20000, seed=5)
+    got = acc[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    nf.sync()
+    ref = oracle.taylor_forces(b.pos[idx], b.box, b.K, p, T)
+    _ty_check(got, ref, b.pos[idx], b.box, b.K, p, T, "taylor clustered sampled")
+    c.free()
+
+
+def test_taylor_rejects_bad_arguments(nf, tiny):
+    b, _ = tiny
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    acc = torch.zeros((b.n, 3), dtype=torch.float32, device="cuda")
+    T11 = torch.zeros((b.K ** 3, 364), dtype=torch.float64, device="cuda")
+    with pytest.raises(nf.NearFieldError):
+        c.taylor_forces(11, T11, acc)
+    with pytest.raises(ValueError):
+        c.taylor_forces(8, torch.zeros((b.K ** 3, 164), dtype=torch.float64, device="cuda"), acc)
+    c.free()

@@ -29,6 +29,12 @@ silent are stated next to each):
 * ``late``      N=2^27, K=256; 50% in 16384 halos with scale radius
   log-uniform in [0.05, 0.5] cell (halo count is a reading chosen so that the
   top 1% of cells hold about half of the particles); masses as ``clustered``.
+
+Synthetic far-field coefficients (``taylor_coefficients``): the paper obtains
+them from a convolution that is not part of this code, so every component of
+total degree n is drawn as amp * z * r0^-n with z standard normal (PCG64, seed),
+a decay like that of the derivatives of 1/r at r0 cell widths (reading: r0 = 3,
+the nearest far-field cells; amp chosen per use).
 """
 from __future__ import annotations
 
@@ -262,3 +268,11 @@ def sample_sinks(n: int, m: int, seed: int = 99) -> np.ndarray:
         return np.arange(n, dtype=np.int64)
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(n, size=m, replace=False)).astype(np.int64)
+
+
+def taylor_coefficients(n_cells: int, p: int, seed: int = 7, amp: float = 1.0, r0: float = 3.0) -> np.ndarray:
+    """[n_cells, (p+1)(p+2)(p+3)/6] float64: degree-n components drawn as amp * N(0,1) * r0^-n, components
+    grouped by degree (lowest first; the order within a degree carries no meaning for the draw)."""
+    rng = np.random.default_rng(seed)
+    scale = np.concatenate([np.full((n + 1) * (n + 2) // 2, amp * r0 ** -n) for n in range(p + 1)])
+    return rng.standard_normal((n_cells, scale.size)) * scale
