@@ -13,6 +13,8 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   each cell centre, positions in cell widths (a reading of the basis).
 * far field from per-cell Taylor series (Sec. 3.1): -grad of the series about
   each cell centre, co-added to a force array.
+* ``kdk.py``: leapfrog kick / drift in the stored FP32 format, the cell
+  timestep criterion, and kick-drift-kick steps over a force callable.
 * ``brute.py``: an independent NumPy all-pairs x 27-image enumeration for tiny
   inputs, which keeps a pair exactly when its cell offset lies in [-R, R]^3.
 
