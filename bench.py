@@ -107,9 +107,10 @@ def main():
     ap.add_argument("--tuning", default="", help="comma list k=v of abacus_nf_tuning fields")
     ap.add_argument("--density", action="store_true",
                     help="also compute the fused kernel density estimate (b = 0.4 x mean spacing per box)")
-    ap.add_argument("--stage", default="forces", choices=["forces", "multipoles", "taylor"],
+    ap.add_argument("--stage", default="forces", choices=["forces", "multipoles", "taylor", "kdk"],
                     help="forces: the near-field step (default); multipoles: cell multipoles of the layout; "
-                         "taylor: far field of synthetic per-cell Taylor series co-added to the accelerations")
+                         "taylor: far field of synthetic per-cell Taylor series co-added to the accelerations; "
+                         "kdk: leapfrog steps (half kick, drift, rebuild, near-field forces, half kick)")
     ap.add_argument("--order", type=int, default=8, help="series order for --stage multipoles / taylor")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a known-size kernel that "
@@ -148,6 +149,9 @@ def main():
         return
     if args.stage == "taylor":
         print(json.dumps(run_taylor(args, nf, torch, gen, w, pos, boxes, acc)), flush=True)
+        return
+    if args.stage == "kdk":
+        print(json.dumps(run_kdk(args, nf, torch, w, pos, boxes, eps, gm, acc)), flush=True)
         return
     threads = min(16, os.cpu_count() or 1)
     samples = {}
@@ -319,6 +323,42 @@ def run_taylor(args, nf, torch, gen, w, pos, boxes, acc):
             "config": {"workload": f"{args.workload}: {w.description}", "n": n, "cells": nc,
                        "occupied_cells": occupied, "order": p, "components": ncomp},
             "roofline": _roofline(nbytes, flops, ms, "k_taylor")}
+
+
+def run_kdk(args, nf, torch, w, pos, boxes, eps, gm, acc):
+    """Leapfrog steps of the near field: each step is half kick, drift, rebuild of the cells, forces, half
+    kick.  The step size comes once from the cell criterion (eta = 0.25) on seeded velocities; the kick and
+    drift kernels are also timed alone (each streams 36 bytes per particle)."""
+    kind, mode = KINDS[args.kind.split(",")[0]], MODES[args.mode.split(",")[0]]
+    cells = nf.build_cells(pos, boxes, 2)
+    if not args.no_tune:
+        cells.autotune(eps, gm, kind, mode, cache_path=args.tune_cache)
+    n = w.n_total
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    vel = 1e-3 * torch.randn((n, 3), generator=g, device="cuda", dtype=torch.float32)
+    cells.forces(eps, gm, kind, mode, out=acc)
+    dt = cells.timestep(vel, acc, 0.25)
+    pairs = cells.interactions()
+    ms = _time_calls(args, torch, nf, lambda: cells.kdk_step(dt, eps, gm, pos, vel, acc, kind, mode))
+    probe = torch.empty_like(vel)
+    kick_ms = _time_calls(args, torch, nf, lambda: cells.kick(dt, acc, probe))
+    drift_ms = _time_calls(args, torch, nf, lambda: cells.drift([0.0] * len(boxes), probe, pos))
+    stream_bytes = 36 * n
+    line = {"metric": "leapfrog steps: particle updates/s (near field)", "value": n / (ms / 1e3),
+            "unit": "particle updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"{args.workload}: {w.description}", "n": n, "boxes": len(boxes),
+                       "kind": args.kind.split(",")[0], "mode": args.mode.split(",")[0], "dt": dt,
+                       "interactions_per_step_at_start": pairs, "tuning": cells.get_tuning().as_dict()},
+            "interactions_per_s_at_start": pairs / (ms / 1e3),
+            "kick": {"ms": kick_ms, "GB/s": stream_bytes / (kick_ms / 1e3) / 1e9,
+                     "frac_hbm": stream_bytes / (kick_ms / 1e3) / 1e9 / 8000.0},
+            "drift": {"ms": drift_ms, "GB/s": stream_bytes / (drift_ms / 1e3) / 1e9,
+                      "frac_hbm": stream_bytes / (drift_ms / 1e3) / 1e9 / 8000.0}}
+    cells.free()
+    return line
 
 
 def _cells_of(b):

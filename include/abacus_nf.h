@@ -163,10 +163,11 @@ int abacus_nf_forces_density(abacus_nf_cells cells, const double *eps, abacus_nf
  *   mass   host double [n_boxes]: particle mass m of each box.
  *   out    device float64 [n_cells][components], cells in global order (box by
  *          box, (cx*K + cy)*K + cz within a box); every cell is written.
- * Sums are FP64 in a fixed order (deterministic): cells with more than 2048
- * particles are cut into units of 2048 whose partial moments are added in order.
- * The first call on a handle (or one with a higher order or a larger batch)
- * allocates the unit bookkeeping; later calls allocate nothing.
+ * Sums are FP64 in a fixed order (deterministic): the sorted particles are cut
+ * into units of 1024 slots; a cell that spans several units gets the partial
+ * moments of its units added in unit order.  The first call on a handle (or one
+ * with a higher order or a larger batch) allocates the partials buffer
+ * (2 x units x components doubles); later calls allocate nothing.
  */
 int abacus_nf_multipoles(abacus_nf_cells cells, int32_t order, const double *mass, double *out, void *hip_stream);
 
@@ -187,6 +188,58 @@ int abacus_nf_multipoles(abacus_nf_cells cells, int32_t order, const double *mas
  */
 int abacus_nf_taylor_forces(abacus_nf_cells cells, int32_t order, const double *taylor, float *acc,
                             void *hip_stream);
+
+/*
+ * Leapfrog time stepping (Sec. 2 "time stepping": second-order kick-drift-kick
+ * leapfrog with one global step per simulation; Sec. 3.1: singlestep kicks,
+ * drifts and moves particles to their new cells before the next force
+ * evaluation).  Positions, velocities and accelerations are device float32
+ * [n_total][3] in input order.  A kick v + a dt and a drift x + v dt are
+ * evaluated in FP64 from the stored FP32 values, the product rounded before the
+ * sum (no fused multiply-add), and rounded once to FP32; a drifted coordinate y
+ * is wrapped into [0, L) as y - L floor(y / L), and stored as 0 if its FP32
+ * rounding reaches L.  dt is host double [n_boxes], one step per box (each box
+ * is an independent simulation; may be negative, must be finite).
+ */
+
+/* abacus_nf_kick -- vel += acc * dt.  Needs a handle that has been built once (for the boxes). */
+int abacus_nf_kick(abacus_nf_cells cells, const double *dt, const float *acc, float *vel, void *hip_stream);
+
+/*
+ * abacus_nf_drift -- pos += vel * dt, wrapped into each box.  The handle's cells
+ * then describe the old positions: forces, multipoles, Taylor forces and
+ * timestep return ESTATE until abacus_nf_build_cells is called again.
+ */
+int abacus_nf_drift(abacus_nf_cells cells, const double *dt, const float *vel, float *pos, void *hip_stream);
+
+/*
+ * abacus_nf_timestep -- the step-size criterion (Sec. 2 "time stepping"):
+ *     dt_b = eta * min over the cells c of box b of sigma_c / max_{j in c} |a_j|,
+ * sigma_c^2 = (1/n_c) sum_{j in c} |v_j - mean_c(v)|^2 (all three components).
+ * Cells with fewer than two particles or no nonzero acceleration do not
+ * constrain the step; a box without a constraining cell gets +inf.  The cells
+ * must be built from the positions the velocities and accelerations belong to.
+ *   eta     > 0 (AbacusSummit uses 0.25).
+ *   dt_out  host double [n_boxes].
+ * Sums are FP64 (velocities taken relative to the first particle of each
+ * cell); the minimum is exact.  Blocks on the stream (copies n_boxes doubles
+ * to the host).  The first call (or one with a larger batch) allocates its
+ * partials buffer.
+ */
+int abacus_nf_timestep(abacus_nf_cells cells, const float *vel, const float *acc, double eta, double *dt_out,
+                       void *hip_stream);
+
+/*
+ * abacus_nf_kdk_step -- one leapfrog step of size dt per box, near field only:
+ *     vel += acc dt/2; pos += vel dt; build the cells again (same boxes and R);
+ *     acc = near-field force at the new positions; vel += acc dt/2.
+ * On entry acc must hold the accelerations at the current positions (an
+ * abacus_nf_forces call on this handle, or the previous step); on return it
+ * holds those at the new positions, ready for the next step.  eps, kind, gm,
+ * mode as for abacus_nf_forces.  Errors as for the calls it makes.
+ */
+int abacus_nf_kdk_step(abacus_nf_cells cells, const double *dt, const double *eps, abacus_nf_kind kind,
+                       const double *gm, abacus_nf_sum mode, float *pos, float *vel, float *acc, void *hip_stream);
 
 /*
  * abacus_nf_sync -- wait for the stream, then return (and clear) the first

@@ -67,6 +67,11 @@ def library():
                                      ctypes.POINTER(d), vp, vp, vp],
         "abacus_nf_multipoles": [vp, i32, ctypes.POINTER(d), vp, vp],
         "abacus_nf_taylor_forces": [vp, i32, vp, vp, vp],
+        "abacus_nf_kick": [vp, ctypes.POINTER(d), vp, vp, vp],
+        "abacus_nf_drift": [vp, ctypes.POINTER(d), vp, vp, vp],
+        "abacus_nf_timestep": [vp, vp, vp, d, ctypes.POINTER(d), vp],
+        "abacus_nf_kdk_step": [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d),
+                               ctypes.c_int, vp, vp, vp, vp],
         "abacus_nf_sync": [vp],
         "abacus_nf_free_cells": [vp],
         "abacus_nf_interactions": [vp, vp, ctypes.POINTER(i64)],
@@ -216,6 +221,46 @@ class Cells:
                                                ctypes.c_void_p(_stream_handle(stream)))
         _check(rc, "abacus_nf_taylor_forces")
         return acc
+
+    def _vec3(self, t, what):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+                and t.shape == (self.n_total, 3) and t.is_contiguous()):
+            raise ValueError(f"{what} must be a contiguous float32 [N,3] GPU tensor")
+        return ctypes.c_void_p(t.data_ptr() if t.numel() else None)
+
+    def kick(self, dt: Sequence[float], acc, vel, stream=None):
+        """abacus_nf_kick: vel += acc * dt (per box), in place."""
+        rc = library().abacus_nf_kick(self._h, _doubles(dt), self._vec3(acc, "acc"), self._vec3(vel, "vel"),
+                                      ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_kick")
+        return vel
+
+    def drift(self, dt: Sequence[float], vel, pos, stream=None):
+        """abacus_nf_drift: pos += vel * dt wrapped into each box, in place (the cells must be built again)."""
+        rc = library().abacus_nf_drift(self._h, _doubles(dt), self._vec3(vel, "vel"), self._vec3(pos, "pos"),
+                                       ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_drift")
+        return pos
+
+    def timestep(self, vel, acc, eta: float = 0.25, stream=None) -> List[float]:
+        """abacus_nf_timestep: eta * min over cells of sigma_v / max|a|, per box (blocks on the stream)."""
+        out = (ctypes.c_double * len(self.boxes))()
+        rc = library().abacus_nf_timestep(self._h, self._vec3(vel, "vel"), self._vec3(acc, "acc"), float(eta), out,
+                                          ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_timestep")
+        return list(out)
+
+    def kdk_step(self, dt: Sequence[float], eps: Sequence[float], gm: Sequence[float], pos, vel, acc,
+                 kind: int = SPLINE, mode: int = SUM_COMP32, stream=None):
+        """abacus_nf_kdk_step: one leapfrog step (half kick, drift, rebuild, forces, half kick), in place.
+        acc must hold the accelerations at the current positions."""
+        rc = library().abacus_nf_kdk_step(self._h, _doubles(dt), _doubles(eps), int(kind), _doubles(gm), int(mode),
+                                          self._vec3(pos, "pos"), self._vec3(vel, "vel"), self._vec3(acc, "acc"),
+                                          ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_kdk_step")
+        self._pos_ref = pos
+        return pos, vel, acc
 
     def interactions(self, stream=None) -> int:
         v = ctypes.c_int64(0)

@@ -33,13 +33,16 @@ struct abacus_nf_cells_s {
     void *scan_temp = nullptr;
     BoxDev *d_boxes = nullptr;
     double *d_mass = nullptr;  // per-box mass for the multipoles
-    // multipole work units (allocated by the first multipoles call of a batch shape)
-    int64_t mcap_cells = -1, mcap_slots = -1;
-    int mcap_comp = -1;
-    int64_t *mp_unit_cnt = nullptr, *mp_heavy_cnt = nullptr, *mp_unit_base = nullptr, *mp_heavy_base = nullptr;
-    int32_t *mp_heavy_list = nullptr, *mp_heavy_n = nullptr;
+    // partial moments of the multipole work units (allocated by the first multipoles call that needs more)
+    size_t mp_cap = 0;
     double *mp_partials = nullptr;
-    void *mp_scan_temp = nullptr;
+
+    // leapfrog: per-box step sizes (kick, drift), timestep partials and per-box minima
+    int scap_boxes = -1;
+    double *d_dt = nullptr;                 // [2][n_boxes]
+    unsigned long long *ts_min = nullptr;   // [n_boxes]
+    size_t ts_cap = 0;
+    double *ts_partials = nullptr;
 
     // force work buffers
     int64_t wcap_cells = -1, wcap_items = -1, wcap_partials = -1, wcap_boxes = -1;
@@ -121,12 +124,16 @@ void mark(abacus_nf_cells_s *h, int stage, bool end, hipStream_t st) {
 }
 
 void free_mp_buffers(abacus_nf_cells_s *h) {
-    dfree(h->mp_unit_cnt); dfree(h->mp_heavy_cnt); dfree(h->mp_unit_base); dfree(h->mp_heavy_base);
-    dfree(h->mp_heavy_list); dfree(h->mp_heavy_n); dfree(h->mp_partials);
-    if (h->mp_scan_temp) hipFree(h->mp_scan_temp);
-    h->mp_scan_temp = nullptr;
-    h->mcap_cells = h->mcap_slots = -1;
-    h->mcap_comp = -1;
+    dfree(h->mp_partials);
+    h->mp_cap = 0;
+}
+
+void free_step_buffers(abacus_nf_cells_s *h) {
+    dfree(h->d_dt);
+    dfree(h->ts_min);
+    dfree(h->ts_partials);
+    h->scap_boxes = -1;
+    h->ts_cap = 0;
 }
 
 void free_work_buffers(abacus_nf_cells_s *h) {
@@ -449,34 +456,14 @@ int abacus_nf_multipoles(abacus_nf_cells h, int32_t order, const double *mass, d
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
     if (dev != h->device) return ABACUS_NF_ESTATE;
-    const int64_t nc = std::max<int64_t>(h->n_cells, 1);
-    const int64_t slots = (int64_t)multipole_scratch_slots(h->n_total, h->n_cells);
-    const int comp = multipole_components(order);
-    if (h->mcap_cells < nc || h->mcap_slots < slots || h->mcap_comp < comp) {
+    const size_t need = multipole_partial_doubles(h->n_total, order);
+    if (h->mp_cap < need) {
         free_mp_buffers(h);
-        bool ok = dalloc(h->mp_unit_cnt, nc) && dalloc(h->mp_heavy_cnt, nc) && dalloc(h->mp_unit_base, nc) &&
-                  dalloc(h->mp_heavy_base, nc) && dalloc(h->mp_heavy_list, slots) && dalloc(h->mp_heavy_n, 1) &&
-                  dalloc(h->mp_partials, (size_t)slots * comp) &&
-                  dalloc_bytes(h->mp_scan_temp, scan_temp_bytes(nc));
-        if (!ok) {
-            free_mp_buffers(h);
-            return ABACUS_NF_ENOMEM;
-        }
-        h->mcap_cells = nc;
-        h->mcap_slots = slots;
-        h->mcap_comp = comp;
+        if (!dalloc(h->mp_partials, need)) return ABACUS_NF_ENOMEM;
+        h->mp_cap = need;
     }
-    MultipoleBuffers mb;
-    mb.mass = h->d_mass;
-    mb.unit_cnt = h->mp_unit_cnt;
-    mb.heavy_cnt = h->mp_heavy_cnt;
-    mb.unit_base = h->mp_unit_base;
-    mb.heavy_base = h->mp_heavy_base;
-    mb.heavy_list = h->mp_heavy_list;
-    mb.heavy_n = h->mp_heavy_n;
-    mb.partials = h->mp_partials;
-    hipError_t e = launch_multipoles(mb, h->spos, h->cell_start, h->d_boxes, h->n_boxes, h->n_cells, order, mass,
-                                     out, dev, h->mp_scan_temp, (hipStream_t)hip_stream);
+    hipError_t e = launch_multipoles(h->spos, h->keys, h->d_boxes, h->n_boxes, h->n_total, h->n_cells, order, mass,
+                                     h->d_mass, h->mp_partials, out, dev, (hipStream_t)hip_stream);
     return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 
@@ -489,8 +476,126 @@ int abacus_nf_taylor_forces(abacus_nf_cells h, int32_t order, const double *tayl
     if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
     if (dev != h->device) return ABACUS_NF_ESTATE;
     if (h->n_total == 0) return ABACUS_NF_OK;
-    hipError_t e = launch_taylor(h->spos, h->cell_start, h->perm, h->d_boxes, h->n_boxes, h->n_cells, order, taylor,
+    hipError_t e = launch_taylor(h->spos, h->keys, h->perm, h->d_boxes, h->n_boxes, h->n_total, order, taylor,
                                  acc, dev, (hipStream_t)hip_stream);
+    return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
+}
+
+// ---------------------------------------------------------------- leapfrog time stepping (kdk.hip)
+
+static int ensure_step_buffers(abacus_nf_cells_s *h, bool timestep) {
+    if (h->scap_boxes < h->n_boxes) {
+        dfree(h->d_dt);
+        dfree(h->ts_min);
+        h->scap_boxes = -1;
+        if (!dalloc(h->d_dt, 2 * (size_t)h->n_boxes) || !dalloc(h->ts_min, (size_t)h->n_boxes)) {
+            free_step_buffers(h);
+            return ABACUS_NF_ENOMEM;
+        }
+        h->scap_boxes = h->n_boxes;
+    }
+    if (timestep) {
+        const size_t need = timestep_partial_doubles(h->n_total);
+        if (h->ts_cap < need) {
+            dfree(h->ts_partials);
+            h->ts_cap = 0;
+            if (!dalloc(h->ts_partials, need)) return ABACUS_NF_ENOMEM;
+            h->ts_cap = need;
+        }
+    }
+    return ABACUS_NF_OK;
+}
+
+static int step_checks(abacus_nf_cells h, const double *dt, int *dev) {
+    if (!h || !dt) return ABACUS_NF_EINVAL;
+    if (h->n_boxes < 1) return ABACUS_NF_ESTATE;
+    for (int b = 0; b < h->n_boxes; b++)
+        if (!std::isfinite(dt[b])) return ABACUS_NF_EINVAL;
+    if (hipGetDevice(dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (*dev != h->device) return ABACUS_NF_ESTATE;
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_kick(abacus_nf_cells h, const double *dt, const float *acc, float *vel, void *hip_stream) {
+    int dev = 0;
+    int rc = step_checks(h, dt, &dev);
+    if (rc != ABACUS_NF_OK) return rc;
+    if (h->n_total > 0 && (!acc || !vel)) return ABACUS_NF_EINVAL;
+    if ((rc = ensure_step_buffers(h, false)) != ABACUS_NF_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = upload_box_doubles(dt, h->n_boxes, h->d_dt, st);
+    if (e == hipSuccess) e = launch_kick(vel, acc, h->n_total, h->d_boxes, h->n_boxes, h->d_dt, dev, st);
+    return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
+}
+
+int abacus_nf_drift(abacus_nf_cells h, const double *dt, const float *vel, float *pos, void *hip_stream) {
+    int dev = 0;
+    int rc = step_checks(h, dt, &dev);
+    if (rc != ABACUS_NF_OK) return rc;
+    if (h->n_total > 0 && (!vel || !pos)) return ABACUS_NF_EINVAL;
+    if ((rc = ensure_step_buffers(h, false)) != ABACUS_NF_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    double *d = h->d_dt + h->n_boxes;
+    hipError_t e = upload_box_doubles(dt, h->n_boxes, d, st);
+    if (e == hipSuccess) e = launch_drift(pos, vel, h->n_total, h->d_boxes, h->n_boxes, d, dev, st);
+    h->built = false;   // the cells describe the old positions until the next build
+    return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
+}
+
+int abacus_nf_timestep(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
+                       void *hip_stream) {
+    if (!h || !dt_out || !std::isfinite(eta) || !(eta > 0)) return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    if (h->n_total > 0 && (!vel || !acc)) return ABACUS_NF_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (dev != h->device) return ABACUS_NF_ESTATE;
+    int rc = ensure_step_buffers(h, true);
+    if (rc != ABACUS_NF_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = launch_timestep(vel, acc, h->keys, h->perm, h->cell_start, h->d_boxes, h->n_boxes, h->n_total,
+                                   h->ts_partials, h->ts_min, dev, st);
+    if (e != hipSuccess) return hip_fail(e);
+    std::vector<unsigned long long> bits((size_t)h->n_boxes);
+    if (hipMemcpyAsync(bits.data(), h->ts_min, bits.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_fail(hipErrorUnknown);
+    for (int b = 0; b < h->n_boxes; b++) {
+        double r;
+        memcpy(&r, &bits[b], sizeof(double));
+        dt_out[b] = std::isinf(r) ? r : eta * r;
+    }
+    return ABACUS_NF_OK;
+}
+
+int abacus_nf_kdk_step(abacus_nf_cells h, const double *dt, const double *eps, abacus_nf_kind kind,
+                       const double *gm, abacus_nf_sum mode, float *pos, float *vel, float *acc, void *hip_stream) {
+    int dev = 0;
+    int rc = step_checks(h, dt, &dev);
+    if (rc != ABACUS_NF_OK) return rc;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    if ((rc = check_force_args(h, eps, kind, gm, mode, acc)) != ABACUS_NF_OK) return rc;
+    if (h->n_total > 0 && (!pos || !vel)) return ABACUS_NF_EINVAL;
+    if ((rc = ensure_step_buffers(h, false)) != ABACUS_NF_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int nb = h->n_boxes;
+    std::vector<double> half((size_t)nb);
+    for (int b = 0; b < nb; b++) half[b] = 0.5 * dt[b];
+    double *d_half = h->d_dt, *d_full = h->d_dt + nb;
+    hipError_t e = upload_box_doubles(half.data(), nb, d_half, st);
+    if (e == hipSuccess) e = upload_box_doubles(dt, nb, d_full, st);
+    if (e == hipSuccess) e = launch_kick(vel, acc, h->n_total, h->d_boxes, nb, d_half, dev, st);
+    if (e == hipSuccess) e = launch_drift(pos, vel, h->n_total, h->d_boxes, nb, d_full, dev, st);
+    if (e != hipSuccess) return hip_fail(e);
+    // move the particles to their new cells, then the forces at the new positions and the second half kick
+    std::vector<abacus_nf_box> boxes = h->boxes;
+    abacus_nf_cells hh = h;
+    h->built = false;
+    if ((rc = abacus_nf_build_cells(pos, h->n_total, boxes.data(), nb, h->R, hip_stream, &hh)) != ABACUS_NF_OK)
+        return rc;
+    if ((rc = forces_impl(h, eps, kind, gm, mode, nullptr, acc, nullptr, hip_stream)) != ABACUS_NF_OK) return rc;
+    e = launch_kick(vel, acc, h->n_total, h->d_boxes, nb, d_half, dev, st);
     return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 
@@ -524,6 +629,7 @@ int abacus_nf_free_cells(abacus_nf_cells h) {
         free_sort_buffers(h);
         free_work_buffers(h);
         free_mp_buffers(h);
+        free_step_buffers(h);
         destroy_events(h);
         if (cur != h->device) hipSetDevice(cur);
     }

@@ -8,67 +8,62 @@
 //
 //     M_c^(a,b,k) = m * sum_{j in c} u_j^a v_j^b w_j^k,   a + b + k <= p,
 //
-// (u, v, w) = position relative to the cell centre in cell widths.  Work is cut
-// into units of at most kMpTile particles of one cell (a cell with more
-// particles -- a halo core -- becomes several units, so no single wave serialises
-// it).  One wave per unit: every lane owns up to kMaxPerLane components;
-// particles are taken 64 at a time, each lane writes the powers of one particle
-// to LDS, and every lane then adds the particles of the batch to its components
-// in slot order.  A single-unit cell writes its moments directly; the units of
-// a heavy cell write partial moments that k_mp_combine adds in unit order.
-// FP64 throughout and fixed orders, so the result does not depend on scheduling.
+// (u, v, w) = position relative to the cell centre in cell widths.
+//
+// Work is cut by particle: a work unit is kMpUnit consecutive slots of the
+// sorted layout, whatever cells they hold, so every unit carries the same work
+// (a halo core spans several units, a sparse region packs many cells into one).
+// One wave walks its unit in batches of kMpBatch slots: each lane writes one
+// particle's powers to LDS as x^a y^b (a + b <= p) and w^k, then every lane
+// adds the particles of the batch, in slot order, to the components it owns
+// (component i belongs to lane i % 64) with one FMA each.  At each cell
+// boundary the wave writes the cell's moments: directly when the whole cell
+// lies in the unit, else as the unit's head or tail partial, which k_mp_combine
+// adds in unit order.  Empty cells are written as zeros by the unit holding
+// the next occupied cell (or the last unit, for trailing ones).  FP64
+// throughout and fixed orders, so the result does not depend on scheduling.
 #include "nf_internal.h"
 
 namespace anf {
 
 namespace {
 
-constexpr int kMpWaves = 2;   // 2 x 64 lanes x 33 doubles of power tables = 33.8 KB of LDS
 constexpr int kMaxOrder = 10;
-constexpr int kMaxComp = (kMaxOrder + 1) * (kMaxOrder + 2) * (kMaxOrder + 3) / 6;  // 286
-constexpr int kMaxPerLane = (kMaxComp + 63) / 64;                                    // 5
+constexpr int kMpUnit = 1024;   // slots per work unit
+constexpr int kMpBatch = 32;    // slots per LDS power table
 
-constexpr int kMpTile = 2048;  // particles per work unit
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Exponents of component i in the degree / a-descending / b-descending order.
+__device__ inline void decode_comp(int i, int &a, int &b, int &k) {
+    int n = 0;
+    while ((n + 1) * (n + 2) * (n + 3) / 6 <= i) n++;
+    const int r = i - n * (n + 1) * (n + 2) / 6;
+    int m = 0;  // m = n - a; the entries of degree n with a = n - m start at m (m + 1) / 2
+    while ((m + 1) * (m + 2) / 2 <= r) m++;
+    a = n - m;
+    b = m - (r - m * (m + 1) / 2);
+    k = n - a - b;
+}
+
+// Column of x^a y^b in a power-table row: rows a = 0..P, each b = 0..P-a.
+__host__ __device__ constexpr int xy_index(int P1, int a, int b) { return a * P1 - a * (a - 1) / 2 + b; }
 
 struct MpArgs {
     const float4 *spos;
-    const int32_t *cs;
+    const int32_t *keys;   // cell of every slot (sorted)
     const BoxDev *boxes;
-    const double *mass;  // per box (device copy)
+    const double *mass;    // per box (device copy)
     int n_boxes;
+    int64_t n;             // slots
     int64_t n_cells;
-    int p;
-    int ncomp;
-    double *out;
-    const int64_t *unit_base;   // [n_cells] first unit of each cell (exclusive scan of units per cell)
-    const int64_t *heavy_base;  // [n_cells] first partial slot of each multi-unit cell
-    const int64_t *unit_cnt;    // [n_cells] units per cell
-    double *partials;           // [slots][ncomp]
+    double *out;           // [n_cells][components]
+    double *partials;      // [2 per unit][components]: head, tail
 };
-
-// Units per cell (at least one, so every cell is written) and partial slots of multi-unit cells;
-// multi-unit cells are also listed for the combine step.
-__global__ void k_mp_units(const int32_t *__restrict__ cs, int64_t n_cells, int64_t *__restrict__ unit_cnt,
-                           int64_t *__restrict__ heavy_cnt, int32_t *__restrict__ heavy_list,
-                           int32_t *__restrict__ heavy_n) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    const int n = cs[c + 1] - cs[c];
-    const int64_t u = n > kMpTile ? (n + kMpTile - 1) / kMpTile : 1;
-    unit_cnt[c] = u;
-    heavy_cnt[c] = u > 1 ? u : 0;
-    if (u > 1) heavy_list[atomicAdd(heavy_n, 1)] = (int32_t)c;
-}
-
-// Cell of unit k: the last cell whose first unit is <= k.
-__device__ inline int64_t cell_of_unit(const int64_t *__restrict__ base, int64_t n_cells, int64_t k) {
-    int64_t lo = 0, hi = n_cells - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (base[mid] <= k) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 constexpr int kMpChunk = 24;
 struct MassChunk {
@@ -81,102 +76,160 @@ __global__ void k_set_mass(MassChunk c, double *dst) {
     if (i < c.count) dst[c.first + i] = c.m[i];
 }
 
-__global__ __launch_bounds__(64 * kMpWaves) void k_multipoles(MpArgs a) {
-    __shared__ double powt[kMpWaves][64][3 * (kMaxOrder + 1)];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int P = a.p, P1 = P + 1;
-    double(*pt)[3 * (kMaxOrder + 1)] = powt[wave];
+__global__ void k_zero_f64(double *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
 
-    // exponents of this lane's components: degree n, then a = n..0, then b = n-a..0
-    int ea[kMaxPerLane], eb[kMaxPerLane], ek[kMaxPerLane];
-    int nmine = 0;
-    {
-        int idx = 0;
-        for (int n = 0; n <= P; n++)
-            for (int x = n; x >= 0; x--)
-                for (int y = n - x; y >= 0; y--, idx++)
-                    if (idx % 64 == lane && nmine < kMaxPerLane) {
-                        ea[nmine] = x;
-                        eb[nmine] = y;
-                        ek[nmine] = n - x - y;
-                        nmine++;
-                    }
+template <int P>
+__global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
+    constexpr int P1 = P + 1;
+    constexpr int NXY = P1 * (P1 + 1) / 2;
+    constexpr int ROW = NXY + P1 + 1;   // x^a y^b, then w^k, one pad double
+    constexpr int NC = P1 * (P1 + 1) * (P1 + 2) / 6;
+    constexpr int PER = (NC + 63) / 64;
+    __shared__ double tab[kMpBatch * ROW];
+    const int lane = threadIdx.x;
+
+    int cxy[PER], cz[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = lane + 64 * q;
+        int ea = 0, eb = 0, ek = 0;
+        if (i < NC) decode_comp(i, ea, eb, ek);
+        cxy[q] = xy_index(P1, ea, eb);
+        cz[q] = NXY + ek;
     }
 
-    const int64_t wave_id = (int64_t)blockIdx.x * kMpWaves + wave;
-    const int64_t n_waves = (int64_t)gridDim.x * kMpWaves;
-    const int64_t n_units = a.unit_base[a.n_cells - 1] + a.unit_cnt[a.n_cells - 1];
-    for (int64_t k = wave_id; k < n_units; k += n_waves) {
-        const int64_t c = cell_of_unit(a.unit_base, a.n_cells, k);
-        const int64_t t = k - a.unit_base[c];
-        const int64_t units = a.unit_cnt[c];
-        const int cs0 = a.cs[c], ncell = a.cs[c + 1] - cs0;
-        const int first = (int)(t * kMpTile);
-        const int n = min(kMpTile, ncell - first);
-        double acc[kMaxPerLane];
+    const int64_t n_units = (a.n + kMpUnit - 1) / kMpUnit;
+    const unsigned G = gridDim.x;
+    const unsigned per_xcd = G / kQueues;
+    const unsigned vb = (blockIdx.x % kQueues) * per_xcd + blockIdx.x / kQueues;
+    const int64_t chunk = (n_units + G - 1) / G;
+    const int64_t u_begin = (int64_t)vb * chunk;
+    const int64_t u_end = u_begin + chunk < n_units ? u_begin + chunk : n_units;
+    const double m0 = a.mass[0];
+
+    for (int64_t u = u_begin; u < u_end; u++) {
+        const int64_t s0 = u * kMpUnit;
+        const int64_t s1 = s0 + kMpUnit < a.n ? s0 + kMpUnit : a.n;
+        int prev_key = s0 > 0 ? a.keys[s0 - 1] : -1;          // cell of the slot before the unit
+        const int after_key = s1 < a.n ? a.keys[s1] : -1;      // cell of the slot after it (-1: none)
+        bool started_here = a.keys[s0] != prev_key;            // the current segment's cell began in this unit
+        double acc[PER];
 #pragma unroll
-        for (int q = 0; q < kMaxPerLane; q++) acc[q] = 0.0;
-        for (int j0 = 0; j0 < n; j0 += 64) {
-            const int nb = min(64, n - j0);
-            if (lane < nb) {
-                const float4 s = a.spos[cs0 + first + j0 + lane];
-                const double tt[3] = {(double)s.x, (double)s.y, (double)s.z};
-                for (int d = 0; d < 3; d++) {
-                    double v = 1.0;
-                    pt[lane][d * P1] = 1.0;
-                    for (int q = 1; q <= P; q++) {
-                        v = v * tt[d];
-                        pt[lane][d * P1 + q] = v;
-                    }
+        for (int q = 0; q < PER; q++) acc[q] = 0.0;
+
+        for (int64_t b0 = s0; b0 < s1; b0 += kMpBatch) {
+            const int nb = (int)(s1 - b0 < kMpBatch ? s1 - b0 : kMpBatch);
+            const bool live = lane < nb;
+            const int key = live ? a.keys[b0 + lane] : -2;
+            int nxt = __shfl_down(key, 1);
+            if (lane == nb - 1) nxt = (b0 + nb < s1) ? a.keys[b0 + nb] : ~key;   // the unit's end closes a segment
+            const uint64_t mask = __ballot(live && key != nxt);
+            if (live) {
+                const float4 sp = a.spos[b0 + lane];
+                const double x = sp.x, y = sp.y, z = sp.z;
+                double xp[P1], yp[P1];
+                double *row = tab + lane * ROW;
+                xp[0] = yp[0] = 1.0;
+                row[NXY] = 1.0;
+                double zk = 1.0;
+#pragma unroll
+                for (int q = 1; q <= P; q++) {
+                    xp[q] = xp[q - 1] * x;
+                    yp[q] = yp[q - 1] * y;
+                    zk = zk * z;
+                    row[NXY + q] = zk;
                 }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            for (int j = 0; j < nb; j++) {
 #pragma unroll
-                for (int q = 0; q < kMaxPerLane; q++)
-                    if (q < nmine) acc[q] += (pt[j][ea[q]] * pt[j][P1 + eb[q]]) * pt[j][2 * P1 + ek[q]];
+                for (int ea = 0; ea <= P; ea++)
+#pragma unroll
+                    for (int eb = 0; eb + ea <= P; eb++) row[xy_index(P1, ea, eb)] = xp[ea] * yp[eb];
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            wave_sync();
+            int j = 0;
+            while (j < nb) {
+                const uint64_t rest = mask >> j;
+                const int e = rest ? j + __builtin_ctzll(rest) : nb - 1;
+                for (int t = j; t <= e; t++) {
+                    const double *row = tab + t * ROW;
+#pragma unroll
+                    for (int q = 0; q < PER; q++) acc[q] = fma(row[cxy[q]], row[cz[q]], acc[q]);
+                }
+                if (rest) {
+                    // segment of cell c ends at slot b0 + e
+                    const int c = __builtin_amdgcn_readlane(key, e);
+                    const bool ends_here = (b0 + e + 1 < s1) || after_key != c;
+                    if (started_here) {
+                        // empty cells between the previous occupied cell and this one
+                        double *z = a.out + (int64_t)(prev_key + 1) * NC;
+                        const int64_t nz = (int64_t)(c - prev_key - 1) * NC;
+                        for (int64_t i = lane; i < nz; i += 64) z[i] = 0.0;
+                    }
+                    double *o;
+                    double scale = 1.0;
+                    if (started_here && ends_here) {
+                        o = a.out + (int64_t)c * NC;
+                        scale = a.n_boxes > 1 ? a.mass[box_of_cell(a.boxes, a.n_boxes, c)] : m0;
+                    } else {
+                        o = a.partials + (2 * u + (started_here ? 1 : 0)) * NC;
+                    }
+#pragma unroll
+                    for (int q = 0; q < PER; q++) {
+                        if (lane + 64 * q < NC) o[lane + 64 * q] = scale * acc[q];
+                        acc[q] = 0.0;
+                    }
+                    prev_key = c;
+                    started_here = true;
+                }
+                j = e + 1;
+            }
+            wave_sync();
         }
-        if (units == 1) {
-            const int b = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, (int32_t)c) : 0;
-            const double m = a.mass[b];
-            double *o = a.out + c * a.ncomp;
-#pragma unroll
-            for (int q = 0; q < kMaxPerLane; q++)
-                if (q < nmine) o[lane + 64 * q] = m * acc[q];
-        } else {
-            double *o = a.partials + (a.heavy_base[c] + t) * a.ncomp;
-#pragma unroll
-            for (int q = 0; q < kMaxPerLane; q++)
-                if (q < nmine) o[lane + 64 * q] = acc[q];
+        if (s1 == a.n) {
+            // trailing empty cells
+            double *z = a.out + (int64_t)(prev_key + 1) * NC;
+            const int64_t nz = (a.n_cells - 1 - prev_key) * NC;
+            for (int64_t i = lane; i < nz; i += 64) z[i] = 0.0;
         }
     }
 }
 
-// Moments of multi-unit cells: the partial moments of their units, added in unit order.
-__global__ __launch_bounds__(64) void k_mp_combine(const int32_t *__restrict__ heavy_list,
-                                                   const int32_t *__restrict__ heavy_n,
-                                                   const int64_t *__restrict__ heavy_base,
-                                                   const int64_t *__restrict__ unit_cnt,
-                                                   const double *__restrict__ partials,
-                                                   const BoxDev *__restrict__ boxes, int n_boxes,
-                                                   const double *__restrict__ mass, int ncomp,
-                                                   double *__restrict__ out) {
-    const int nh = *heavy_n;
-    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
-        const int32_t c = heavy_list[h];
-        const int64_t units = unit_cnt[c], base = heavy_base[c];
-        const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, c) : 0;
-        const double m = mass[b];
-        for (int q = threadIdx.x; q < ncomp; q += 64) {
-            double t = 0.0;
-            for (int64_t u = 0; u < units; u++) t += partials[(base + u) * ncomp + q];
-            out[(int64_t)c * ncomp + q] = m * t;
+// Moments of the cells that cross unit boundaries: the tail partial of the unit where the cell begins,
+// then the head partials of the units it continues into, added in unit order.
+template <int P>
+__global__ __launch_bounds__(64) void k_mp_combine(MpArgs a) {
+    constexpr int P1 = P + 1;
+    constexpr int NC = P1 * (P1 + 1) * (P1 + 2) / 6;
+    const int64_t n_units = (a.n + kMpUnit - 1) / kMpUnit;
+    for (int64_t u = 1 + blockIdx.x; u < n_units; u += gridDim.x) {
+        const int c = a.keys[u * kMpUnit];
+        if (a.keys[u * kMpUnit - 1] != c) continue;                          // no cell crosses here
+        if (u >= 2 && a.keys[(u - 1) * kMpUnit - 1] == c) continue;          // crossed an earlier boundary
+        int64_t last = u;
+        while (last + 1 < n_units && a.keys[(last + 1) * kMpUnit] == c) last++;
+        const double m = a.n_boxes > 1 ? a.mass[box_of_cell(a.boxes, a.n_boxes, c)] : a.mass[0];
+        for (int i = threadIdx.x; i < NC; i += 64) {
+            double t = a.partials[(2 * (u - 1) + 1) * NC + i];
+            for (int64_t v = u; v <= last; v++) t += a.partials[(2 * v) * NC + i];
+            a.out[(int64_t)c * NC + i] = m * t;
+        }
+    }
+}
+
+typedef void (*MpKernel)(MpArgs);
+
+template <int P>
+void pick_mp(int p, MpKernel &main, MpKernel &combine) {
+    if constexpr (P > kMaxOrder) {
+        main = combine = nullptr;
+    } else {
+        if (p == P) {
+            main = k_multipoles<P>;
+            combine = k_mp_combine<P>;
+        } else {
+            pick_mp<P + 1>(p, main, combine);
         }
     }
 }
@@ -187,56 +240,54 @@ int multipole_components(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
 int multipole_max_order() { return kMaxOrder; }
 
-size_t multipole_scratch_slots(int64_t n_total, int64_t n_cells) {
-    // each multi-unit cell holds more than kMpTile particles and at most 2 n_c / kMpTile units
-    (void)n_cells;
-    return (size_t)(2 * n_total / kMpTile + 1);
+size_t multipole_partial_doubles(int64_t n_total, int p) {
+    const int64_t units = (n_total + kMpUnit - 1) / kMpUnit;
+    return (size_t)(2 * (units > 0 ? units : 1)) * (size_t)multipole_components(p);
 }
 
-int multipole_tile() { return kMpTile; }
-
-hipError_t launch_multipoles(const MultipoleBuffers &mb, const float4 *spos, const int32_t *cs,
-                             const BoxDev *boxes, int n_boxes, int64_t n_cells, int p, const double *mass_host,
-                             double *out, int device, void *scan_temp, hipStream_t st) {
+hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const BoxDev *boxes, int n_boxes, int64_t n,
+                             int64_t n_cells, int p, const double *mass_host, double *mass_dev, double *partials,
+                             double *out, int device, hipStream_t st) {
+    MpKernel kmain = nullptr, kcomb = nullptr;
+    pick_mp<0>(p, kmain, kcomb);
+    if (!kmain) return hipErrorInvalidValue;
     for (int first = 0; first < n_boxes; first += kMpChunk) {
         MassChunk ch;
         ch.first = first;
         ch.count = n_boxes - first < kMpChunk ? n_boxes - first : kMpChunk;
         for (int k = 0; k < kMpChunk; k++) ch.m[k] = k < ch.count ? mass_host[first + k] : 0.0;
-        hipLaunchKernelGGL(k_set_mass, dim3(1), dim3(kMpChunk), 0, st, ch, mb.mass);
+        hipLaunchKernelGGL(k_set_mass, dim3(1), dim3(kMpChunk), 0, st, ch, mass_dev);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n_cells <= 0) return hipSuccess;
-    hipError_t e = launch_fill_i32(mb.heavy_n, 1, 0, st);
-    if (e != hipSuccess) return e;
-    const unsigned gc = (unsigned)((n_cells + 255) / 256);
-    hipLaunchKernelGGL(k_mp_units, dim3(gc), dim3(256), 0, st, cs, n_cells, mb.unit_cnt, mb.heavy_cnt,
-                       mb.heavy_list, mb.heavy_n);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = scan_i64_add_exclusive(mb.unit_cnt, mb.unit_base, n_cells, scan_temp, st)) != hipSuccess) return e;
-    if ((e = scan_i64_add_exclusive(mb.heavy_cnt, mb.heavy_base, n_cells, scan_temp, st)) != hipSuccess) return e;
-    MpArgs a;
-    a.spos = spos;
-    a.cs = cs;
-    a.boxes = boxes;
-    a.mass = mb.mass;
-    a.n_boxes = n_boxes;
-    a.n_cells = n_cells;
-    a.p = p;
-    a.ncomp = multipole_components(p);
-    a.out = out;
-    a.unit_base = mb.unit_base;
-    a.heavy_base = mb.heavy_base;
-    a.unit_cnt = mb.unit_cnt;
-    a.partials = mb.partials;
     int cus = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
-    const unsigned grid = (unsigned)cus * 16;
-    hipLaunchKernelGGL(k_multipoles, dim3(grid), dim3(64 * kMpWaves), 0, st, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mp_combine, dim3((unsigned)cus * 4), dim3(64), 0, st, mb.heavy_list, mb.heavy_n,
-                       mb.heavy_base, mb.unit_cnt, mb.partials, boxes, n_boxes, mb.mass, a.ncomp, out);
+    const int64_t ncomp = multipole_components(p);
+    if (n <= 0) {
+        const int64_t total = n_cells * ncomp;
+        const int64_t blocks = std::min<int64_t>((total + 255) / 256, (int64_t)cus * 16);
+        hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)blocks), dim3(256), 0, st, out, total);
+        return hipGetLastError();
+    }
+    MpArgs a;
+    a.spos = spos;
+    a.keys = keys;
+    a.boxes = boxes;
+    a.mass = mass_dev;
+    a.n_boxes = n_boxes;
+    a.n = n;
+    a.n_cells = n_cells;
+    a.out = out;
+    a.partials = partials;
+    const int64_t n_units = (n + kMpUnit - 1) / kMpUnit;
+    int64_t grid = std::min<int64_t>(n_units, (int64_t)cus * 16);
+    grid = (grid + kQueues - 1) / kQueues * kQueues;
+    hipLaunchKernelGGL(kmain, dim3((unsigned)grid), dim3(64), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_units < 2) return e;
+    const int64_t cgrid = std::min<int64_t>(n_units - 1, (int64_t)cus * 8);
+    hipLaunchKernelGGL(kcomb, dim3((unsigned)cgrid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -122,28 +122,17 @@ hipError_t launch_gather(const float *pos, const int32_t *perm, const int32_t *k
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 
 // Cell multipoles (multipoles.hip)
-struct MultipoleBuffers {
-    double *mass;          // [n_boxes]
-    int64_t *unit_cnt;     // [n_cells]
-    int64_t *heavy_cnt;    // [n_cells]
-    int64_t *unit_base;    // [n_cells]
-    int64_t *heavy_base;   // [n_cells]
-    int32_t *heavy_list;   // [scratch slots]
-    int32_t *heavy_n;      // [1]
-    double *partials;      // [scratch slots][components]
-};
 int multipole_components(int p);
 int multipole_max_order();
-int multipole_tile();
-size_t multipole_scratch_slots(int64_t n_total, int64_t n_cells);
-hipError_t launch_multipoles(const MultipoleBuffers &mb, const float4 *spos, const int32_t *cs,
-                             const BoxDev *boxes, int n_boxes, int64_t n_cells, int p, const double *mass_host,
-                             double *out, int device, void *scan_temp, hipStream_t st);
+size_t multipole_partial_doubles(int64_t n_total, int p);   // unit partials buffer size
+hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const BoxDev *boxes, int n_boxes, int64_t n,
+                             int64_t n_cells, int p, const double *mass_host, double *mass_dev, double *partials,
+                             double *out, int device, hipStream_t st);
 
 // Far field from cell Taylor series (taylor.hip)
 int taylor_max_order();
-hipError_t launch_taylor(const float4 *spos, const int32_t *cs, const int32_t *perm, const BoxDev *boxes,
-                         int n_boxes, int64_t n_cells, int p, const double *taylor, float *acc, int device,
+hipError_t launch_taylor(const float4 *spos, const int32_t *keys, const int32_t *perm, const BoxDev *boxes,
+                         int n_boxes, int64_t n, int p, const double *taylor, float *acc, int device,
                          hipStream_t st);
 
 // Work list and forces (forces.hip)
@@ -184,5 +173,16 @@ hipError_t launch_forces(const ForcesArgs &a, hipStream_t st);
 hipError_t launch_finalize(const ForcesArgs &a, hipStream_t st);
 int forces_grid(const abacus_nf_tuning &t, abacus_nf_kind kind, abacus_nf_sum mode, bool kde, int device);
 hipError_t launch_count_interactions(const ForcesArgs &a, hipStream_t st);
+
+// Leapfrog time stepping (kdk.hip)
+hipError_t upload_box_doubles(const double *host, int n_boxes, double *dev, hipStream_t st);
+hipError_t launch_kick(float *vel, const float *acc, int64_t n, const BoxDev *boxes, int n_boxes, const double *dt,
+                       int device, hipStream_t st);
+hipError_t launch_drift(float *pos, const float *vel, int64_t n, const BoxDev *boxes, int n_boxes, const double *dt,
+                        int device, hipStream_t st);
+size_t timestep_partial_doubles(int64_t n);
+hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *keys, const int32_t *perm,
+                           const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, double *partials,
+                           unsigned long long *dmin, int device, hipStream_t st);
 
 }  // namespace anf

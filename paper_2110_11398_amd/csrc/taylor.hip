@@ -8,10 +8,17 @@
 //     Phi = sum_{a+b+k <= p} T^(a,b,k) u^a v^b w^k,
 // the far field is -grad_x Phi = -(K/L) grad_u Phi, added to acc.
 //
-// One wave per cell: the cell's coefficients are staged in LDS and read as
-// broadcasts; each lane evaluates one particle.  For every column (b, k) the
-// polynomial P_bk(u) = sum_a T^(a,b,k) u^a and its derivative come from one
-// Horner pass, then
+// Work is cut by particle, not by cell: a wave takes 64 consecutive slots of
+// the cell-sorted layout, so every wave carries the same work whatever the
+// occupancy of the cells (a halo core spans many waves, a sparse region packs
+// several cells into one).  The coefficients of the contiguous range of cells
+// the 64 slots cover are staged in LDS (kTyCells cells at a time) and each lane
+// reads its own cell's block.  Waves on one XCD take one contiguous run of
+// slot batches, so neighbouring batches that share a cell's coefficients share
+// that XCD's L2.
+//
+// Per particle: for every column (b, k) the polynomial P_bk(u) =
+// sum_a T^(a,b,k) u^a and its derivative come from one Horner pass, then
 //     d/du Phi = sum P'_bk v^b w^k,  d/dv Phi = sum P_bk b v^(b-1) w^k,
 //     d/dw Phi = sum P_bk v^b k w^(k-1),
 // all in FP64 with the order p a compile-time constant, so every power stays
@@ -22,9 +29,8 @@ namespace anf {
 
 namespace {
 
-constexpr int kTyWaves = 2;
 constexpr int kTyMaxOrder = 10;
-constexpr int kTyMaxComp = (kTyMaxOrder + 1) * (kTyMaxOrder + 2) * (kTyMaxOrder + 3) / 6;
+constexpr int kTyStageBytes = 8192;   // LDS per wave for staged coefficients (20 waves per CU)
 
 // Position of component (a, b, k) in the degree / a-descending / b-descending order.
 __host__ __device__ constexpr int comp_index(int a, int b, int k) {
@@ -34,37 +40,60 @@ __host__ __device__ constexpr int comp_index(int a, int b, int k) {
 
 struct TyArgs {
     const float4 *spos;
-    const int32_t *cs;
-    const int32_t *perm;
+    const int32_t *keys;   // cell of every slot (sorted)
+    const int32_t *perm;   // input index of every slot
     const BoxDev *boxes;
     int n_boxes;
-    int64_t n_cells;
+    int64_t n;             // particles (slots)
     const double *taylor;
     float *acc;
 };
 
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 template <int P>
-__global__ __launch_bounds__(64 * kTyWaves) void k_taylor(TyArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 9 ? 2 : 4, 8))) void k_taylor(TyArgs a) {
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
-    __shared__ double tc[kTyWaves][NC > 0 ? NC : 1];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *T = tc[wave];
-    const int64_t wave_id = (int64_t)blockIdx.x * kTyWaves + wave;
-    const int64_t n_waves = (int64_t)gridDim.x * kTyWaves;
-    for (int64_t c = wave_id; c < a.n_cells; c += n_waves) {
-        const int cs0 = a.cs[c], n = a.cs[c + 1] - cs0;
-        if (n == 0) continue;
-        for (int q = lane; q < NC; q += 64) T[q] = a.taylor[c * NC + q];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const int bi = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, (int32_t)c) : 0;
-        const double s = a.boxes[bi].s;
-        for (int j0 = 0; j0 < n; j0 += 64) {
-            if (j0 + lane < n) {
-                const int slot = cs0 + j0 + lane;
-                const float4 sp = a.spos[slot];
-                const double u = sp.x, v = sp.y, w = sp.z;
+    constexpr int kCells = kTyStageBytes / (NC * 8) > 0 ? kTyStageBytes / (NC * 8) : 1;
+    __shared__ double tc[kCells * NC];
+    const int lane = threadIdx.x;
+    // XCD-aware contiguous chunks: block i runs on XCD i % 8; the blocks of one XCD take adjacent chunks
+    const int64_t n_batches = (a.n + 63) >> 6;
+    const unsigned G = gridDim.x;
+    const unsigned per_xcd = G / kQueues;
+    const unsigned vb = (blockIdx.x % kQueues) * per_xcd + blockIdx.x / kQueues;
+    const int64_t chunk = (n_batches + G - 1) / G;
+    const int64_t b_begin = (int64_t)vb * chunk;
+    const int64_t b_end = b_begin + chunk < n_batches ? b_begin + chunk : n_batches;
+    for (int64_t bt = b_begin; bt < b_end; bt++) {
+        const int64_t slot = bt * 64 + lane;
+        const bool live = slot < a.n;
+        const int key = live ? a.keys[slot] : -1;
+        const int c_lo = __builtin_amdgcn_readfirstlane(key);       // lane 0 is always live
+        const int64_t last = (bt * 64 + 64 < a.n ? bt * 64 + 64 : a.n) - 1;
+        const int c_hi = a.keys[last];
+        double u = 0.0, v = 0.0, w = 0.0, s = 0.0;
+        if (live) {
+            const float4 sp = a.spos[slot];
+            u = sp.x;
+            v = sp.y;
+            w = sp.z;
+            const int bi = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, key) : 0;
+            s = a.boxes[bi].s;
+        }
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int c0 = c_lo; c0 <= c_hi; c0 += kCells) {
+            const int nc = c_hi - c0 + 1 < kCells ? c_hi - c0 + 1 : kCells;
+            wave_sync();
+            const double *src = a.taylor + (int64_t)c0 * NC;
+            for (int i = lane; i < nc * NC; i += 64) tc[i] = src[i];
+            wave_sync();
+            if (live && key >= c0 && key < c0 + nc) {
+                const double *T = tc + (key - c0) * NC;
                 double pv[P + 1], pw[P + 1];
                 pv[0] = pw[0] = 1.0;
 #pragma unroll
@@ -72,7 +101,6 @@ __global__ __launch_bounds__(64 * kTyWaves) void k_taylor(TyArgs a) {
                     pv[q] = pv[q - 1] * v;
                     pw[q] = pw[q - 1] * w;
                 }
-                double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
                 for (int b = 0; b <= P; b++) {
 #pragma unroll
@@ -90,17 +118,18 @@ __global__ __launch_bounds__(64 * kTyWaves) void k_taylor(TyArgs a) {
                         gx += der * vw;
                         if (b > 0) gy += val * (b * pv[b - 1]) * pw[k];
                         if (k > 0) gz += val * pv[b] * (k * pw[k - 1]);
+                        // keep each column's LDS reads next to their use (no hoisting of all of them)
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
-                float *o = a.acc + 3 * (int64_t)a.perm[slot];
-                o[0] = (float)((double)o[0] - s * gx);
-                o[1] = (float)((double)o[1] - s * gy);
-                o[2] = (float)((double)o[2] - s * gz);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (live) {
+            float *o = a.acc + 3 * (int64_t)a.perm[slot];
+            o[0] = (float)((double)o[0] - s * gx);
+            o[1] = (float)((double)o[1] - s * gy);
+            o[2] = (float)((double)o[2] - s * gz);
+        }
     }
 }
 
@@ -119,27 +148,29 @@ TyKernel pick_taylor(int p) {
 
 int taylor_max_order() { return kTyMaxOrder; }
 
-hipError_t launch_taylor(const float4 *spos, const int32_t *cs, const int32_t *perm, const BoxDev *boxes,
-                         int n_boxes, int64_t n_cells, int p, const double *taylor, float *acc, int device,
+hipError_t launch_taylor(const float4 *spos, const int32_t *keys, const int32_t *perm, const BoxDev *boxes,
+                         int n_boxes, int64_t n, int p, const double *taylor, float *acc, int device,
                          hipStream_t st) {
-    if (n_cells <= 0) return hipSuccess;
+    if (n <= 0) return hipSuccess;
     TyKernel kfn = pick_taylor<0>(p);
     if (!kfn) return hipErrorInvalidValue;
     TyArgs a;
     a.spos = spos;
-    a.cs = cs;
+    a.keys = keys;
     a.perm = perm;
     a.boxes = boxes;
     a.n_boxes = n_boxes;
-    a.n_cells = n_cells;
+    a.n = n;
     a.taylor = taylor;
     a.acc = acc;
     int cus = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
-    const int64_t want = (n_cells + kTyWaves - 1) / kTyWaves;
-    const int64_t cap = (int64_t)cus * 32;
-    const unsigned grid = (unsigned)(want < cap ? want : cap);
-    hipLaunchKernelGGL(kfn, dim3(grid), dim3(64 * kTyWaves), 0, st, a);
+    // a multiple of 8 blocks (one share per XCD), at most one 64-slot batch per block
+    const int64_t n_batches = (n + 63) / 64;
+    int64_t grid = (int64_t)cus * 16;
+    if (grid > n_batches) grid = n_batches;
+    grid = (grid + kQueues - 1) / kQueues * kQueues;
+    hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

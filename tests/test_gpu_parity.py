@@ -562,8 +562,8 @@ def _mp_cell_of(n_in_cell, K=8, seed=0):
 
 @pytest.mark.parametrize("n_in_cell", [2047, 2048, 2049, 4096, 6001])
 def test_multipoles_unit_boundaries_and_determinism(nf, n_in_cell):
-    """Cells are cut into units of 2048 particles: one below, at and above a unit boundary, an exact multiple
-    and a ragged last unit; two calls give bit-identical moments."""
+    """The sorted particles are cut into units of 1024 slots, so a heavy cell spans two to seven units whose
+    partials are combined; two calls give bit-identical moments."""
     K = 8
     p = _mp_cell_of(n_in_cell, K)
     c = nf.build_cells(torch.from_numpy(p).cuda(), [(len(p), 1.0, K)], 2)
@@ -700,4 +700,208 @@ def test_taylor_rejects_bad_arguments(nf, tiny):
         c.taylor_forces(11, T11, acc)
     with pytest.raises(ValueError):
         c.taylor_forces(8, torch.zeros((b.K ** 3, 164), dtype=torch.float64, device="cuda"), acc)
+    c.free()
+
+
+# ---------------------------------------------------------------- leapfrog time stepping (Sec. 2, Sec. 3.1)
+
+from oracle import kdk as okdk  # noqa: E402
+
+
+def _boxes_and_state(seed=0, n_boxes=3, lo=10 ** 3, hi=20 ** 3):
+    w = gen.workload("batched", n_boxes=n_boxes, lo=lo, hi=hi)
+    pos = w.concat_positions()
+    rng = np.random.default_rng(seed)
+    vel = (0.01 * rng.standard_normal(pos.shape)).astype(np.float32)
+    acc = (0.1 * rng.standard_normal(pos.shape)).astype(np.float32)
+    return w, pos, vel, acc
+
+
+def test_kick_is_bit_exact(nf):
+    w, pos, vel, acc = _boxes_and_state()
+    dts = [0.013, -0.7, 3.0][:len(w.boxes)]
+    c = nf.build_cells(torch.from_numpy(pos).cuda(), [(b.n, b.box, b.K) for b in w.boxes], 2)
+    v = torch.from_numpy(vel).cuda()
+    c.kick(dts, torch.from_numpy(acc).cuda(), v)
+    got = v.cpu().numpy()
+    nf.sync()
+    off = 0
+    for b, h in zip(w.boxes, dts):
+        ref = okdk.kick(vel[off:off + b.n], acc[off:off + b.n], h)
+        assert np.array_equal(got[off:off + b.n], ref), f"box n={b.n}"
+        off += b.n
+    c.free()
+
+
+def test_drift_is_bit_exact_with_wraps(nf):
+    w, pos, vel, _ = _boxes_and_state(seed=1)
+    rng = np.random.default_rng(2)
+    vel = (rng.standard_normal(pos.shape) * rng.choice([1e-4, 0.3, 5.0], size=pos.shape)).astype(np.float32)
+    # particles at the box edges, velocities that cross one or several boxes, and the round-up-to-L case
+    pos[0] = [0.0, 0.0, 0.0]
+    vel[0] = [-1e-9, 1e-9, 0.0]
+    pos[1] = [np.nextafter(np.float32(1.0), np.float32(0)), 0.5, 0.5]
+    vel[1] = [1e-9, -3.0, 7.0]
+    dts = [0.5, -0.25, 2.0][:len(w.boxes)]
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    c = nf.build_cells(torch.from_numpy(pos).cuda(), boxes, 2)
+    p = torch.from_numpy(pos).cuda()
+    c.drift(dts, torch.from_numpy(vel).cuda(), p)
+    got = p.cpu().numpy()
+    nf.sync()
+    off = 0
+    for b, h in zip(w.boxes, dts):
+        ref = okdk.drift(pos[off:off + b.n], vel[off:off + b.n], h, b.box)
+        assert np.array_equal(got[off:off + b.n], ref), f"box n={b.n}"
+        assert np.all((got[off:off + b.n] >= 0) & (got[off:off + b.n] < b.box))
+        off += b.n
+    # the cells now describe the old positions
+    with pytest.raises(nf.NearFieldError):
+        c.forces([b.eps for b in w.boxes], [b.gm for b in w.boxes])
+    c.free()
+
+
+def _ts_check(got, ref, what):
+    print(f"{what}: gpu {got!r} oracle {ref!r}", flush=True)
+    for g, r in zip(got, ref):
+        if np.isinf(r):
+            assert np.isinf(g) and g > 0, what
+        else:
+            assert abs(g - r) <= 1e-9 * r, what
+
+
+def test_timestep_batched_boxes(nf):
+    w, pos, vel, acc = _boxes_and_state(seed=3, n_boxes=4)
+    c = nf.build_cells(torch.from_numpy(pos).cuda(), [(b.n, b.box, b.K) for b in w.boxes], 2)
+    got = c.timestep(torch.from_numpy(vel).cuda(), torch.from_numpy(acc).cuda(), 0.25)
+    ref, off = [], 0
+    for b in w.boxes:
+        ref.append(okdk.cell_timestep(pos[off:off + b.n], vel[off:off + b.n], acc[off:off + b.n], b.box, b.K, 0.25))
+        off += b.n
+    _ts_check(got, ref, "timestep batched")
+    c.free()
+
+
+def test_timestep_heavy_cells_bulk_flow_and_lone_particles(nf):
+    """Cells of 1000 to 5000 particles (crossing several 1024-slot units), a bulk velocity 10^4 times the
+    dispersion, and a box of lone particles (no constraining cell: +inf)."""
+    rng = np.random.default_rng(4)
+    K = 6
+    cen = (np.array([[1, 2, 3], [4, 4, 4], [0, 5, 1]]) + 0.5) / K
+    parts = [c + 0.02 * rng.standard_normal((n, 3)) for c, n in zip(cen, (1000, 2049, 5000))]
+    p1 = (np.concatenate(parts + [rng.random((300, 3))]) % 1.0).astype(np.float32)
+    v1 = (100.0 + 1e-2 * rng.standard_normal(p1.shape)).astype(np.float32)
+    a1 = rng.standard_normal(p1.shape).astype(np.float32)
+    p2 = ((np.arange(8)[:, None] + 0.5) / 8 * np.ones((1, 3))).astype(np.float32)   # one particle per cell
+    v2 = rng.standard_normal(p2.shape).astype(np.float32)
+    a2 = rng.standard_normal(p2.shape).astype(np.float32)
+    pos = np.concatenate([p1, p2])
+    c = nf.build_cells(torch.from_numpy(pos).cuda(), [(len(p1), 1.0, K), (len(p2), 1.0, 8)], 2)
+    got = c.timestep(torch.from_numpy(np.concatenate([v1, v2])).cuda(),
+                     torch.from_numpy(np.concatenate([a1, a2])).cuda(), 0.25)
+    ref = [okdk.cell_timestep(p1, v1, a1, 1.0, K, 0.25), okdk.cell_timestep(p2, v2, a2, 1.0, 8, 0.25)]
+    _ts_check(got, ref, "timestep heavy / bulk / lone")
+    c.free()
+
+
+def _displacement(a, b, L):
+    d = np.abs(a.astype(np.float64) - b.astype(np.float64))
+    return np.minimum(d, L - d)
+
+
+@pytest.mark.parametrize("kind", [SPLINE, PLUMMER])
+def test_kdk_step_matches_oracle(nf, tiny, kind):
+    """One leapfrog step on the tiny workload with a step that moves particles about a fifth of a cell (many
+    change cells).  Positions: within the drift of the force tolerance plus one FP32 rounding; velocity change:
+    the force-parity statistics on (v1 - v0) / (dt / 2), which equals a(x0) + a(x1)."""
+    b, tref = tiny
+    a0_ref, _, mag0 = tref[kind]
+    w = b.box / b.K
+    amed = float(np.median(np.linalg.norm(a0_ref, axis=1)))
+    dt = float(np.sqrt(0.2 * w / amed))
+    rng = np.random.default_rng(6)
+    vel = (amed * dt * rng.standard_normal((b.n, 3)) / np.sqrt(3)).astype(np.float32)
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    p = torch.from_numpy(b.pos.copy()).cuda()
+    v = torch.from_numpy(vel.copy()).cuda()
+    acc = c.forces([b.eps], [b.gm], kind, 1)
+    c.kdk_step([dt], [b.eps], [b.gm], p, v, acc, kind, 1)
+    xg, vg = p.cpu().numpy(), v.cpu().numpy()
+    nf.sync()
+    f = okdk.near_field(b.box, b.K, 2, b.eps, kind, b.gm)
+    x1, v1, a1 = okdk.kdk_step(b.pos, vel, dt, b.box, f, a0_ref)
+    moved = np.mean(oracle.bin_cells(x1, b.box, b.K) != oracle.bin_cells(b.pos, b.box, b.K))
+    print(f"kdk kind={kind}: dt={dt:.3e}, {100 * moved:.1f}% of particles changed cells", flush=True)
+    assert moved > 0.05
+    # the half-kicked velocity is stored in FP32 on both sides: its roundings may differ by one unit
+    vh = np.linalg.norm(vel.astype(np.float64) + 0.5 * dt * a0_ref, axis=1)
+    dev0 = 1e-3 * np.linalg.norm(a0_ref, axis=1) + 1e-5 * mag0
+    tol_x = 0.5 * dt * dt * dev0 + dt * 2.0 ** -23 * vh + 2.0 ** -23 * b.box
+    dx = _displacement(xg, x1, b.box).max(axis=1)
+    print(f"positions: max dx/tol {np.max(dx / tol_x):.3e}", flush=True)
+    assert np.all(dx <= tol_x), "positions"
+    mag1 = oracle.forces(x1, b.box, b.K, 2, b.eps, kind, b.gm, return_mag=True)[1]
+    eff_g = (vg.astype(np.float64) - vel) / (0.5 * dt)
+    eff_r = (v1.astype(np.float64) - vel) / (0.5 * dt)
+    # statistics as for the forces; per particle, the force bound for both evaluations plus the FP32
+    # roundings of the stored velocities (relative 2^-24 each, divided by dt/2)
+    na = np.linalg.norm(eff_r, axis=1)
+    err = np.linalg.norm(eff_g - eff_r, axis=1)
+    fe = err[na > 0] / na[na > 0]
+    med, p99 = float(np.median(fe)), float(np.percentile(fe, 99))
+    vnorm = vh + np.linalg.norm(v1.astype(np.float64), axis=1)
+    bound = 1e-3 * na + 1e-5 * (mag0 + mag1) + 2.0 ** -22 * vnorm / (0.5 * dt)
+    print(f"kdk velocity change kind={kind}: median={med:.3e} p99={p99:.3e} "
+          f"worst/bound={np.max(err / bound):.3f}", flush=True)
+    assert med <= MED_TOL and p99 <= P99_TOL and np.all(err <= bound)
+    c.free()
+
+
+def test_kdk_step_equals_its_composition(nf, tiny):
+    """abacus_nf_kdk_step is exactly: kick dt/2, drift dt, build, forces, kick dt/2 (bit-identical)."""
+    b, _ = tiny
+    dt = 0.02
+    vel = (0.05 * np.random.default_rng(7).standard_normal((b.n, 3))).astype(np.float32)
+    boxes = [(b.n, b.box, b.K)]
+    c1 = nf.build_cells(torch.from_numpy(b.pos).cuda(), boxes, 2)
+    p1, v1 = torch.from_numpy(b.pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda()
+    a1 = c1.forces([b.eps], [b.gm], SPLINE, 1)
+    for _ in range(2):
+        c1.kdk_step([dt], [b.eps], [b.gm], p1, v1, a1, SPLINE, 1)
+    c2 = nf.build_cells(torch.from_numpy(b.pos).cuda(), boxes, 2)
+    p2, v2 = torch.from_numpy(b.pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda()
+    a2 = c2.forces([b.eps], [b.gm], SPLINE, 1)
+    for _ in range(2):
+        c2.kick([dt / 2], a2, v2)
+        c2.drift([dt], v2, p2)
+        c2.build(p2, boxes, 2)
+        c2.forces([b.eps], [b.gm], SPLINE, 1, out=a2)
+        c2.kick([dt / 2], a2, v2)
+    nf.sync()
+    assert torch.equal(p1, p2) and torch.equal(v1, v2) and torch.equal(a1, a2)
+    c1.free()
+    c2.free()
+
+
+def test_kdk_loop_with_adaptive_step_conserves_momentum(nf):
+    """Ten steps on a clustered box with the step from the cell criterion each time: total momentum is
+    conserved to FP32 accumulation level and every position stays in the box."""
+    w = gen.workload("clustered", side=24, K=8, n_halos=20)
+    b = w.boxes[0]
+    p = torch.from_numpy(b.pos.copy()).cuda()
+    v = torch.from_numpy((1e-3 * np.random.default_rng(9).standard_normal((b.n, 3))).astype(np.float32)).cuda()
+    c = nf.build_cells(p, [(b.n, b.box, b.K)], 2)
+    acc = c.forces([b.eps], [b.gm], SPLINE, 1)
+    v0 = v.double().sum(0)
+    for step in range(10):
+        dt = c.timestep(v, acc, 0.25)[0]
+        assert np.isfinite(dt) and dt > 0
+        c.kdk_step([dt], [b.eps], [b.gm], p, v, acc, SPLINE, 1)
+    nf.sync()
+    pc = p.cpu().numpy()
+    assert np.all((pc >= 0) & (pc < b.box))
+    dv = (v.double().sum(0) - v0).abs().max().item()
+    scale = v.double().abs().sum().item()
+    print(f"momentum drift {dv:.3e} of sum|v| {scale:.3e}", flush=True)
+    assert scale > 0 and dv <= 1e-4 * scale
     c.free()
