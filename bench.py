@@ -112,6 +112,9 @@ def main():
                          "taylor: far field of synthetic per-cell Taylor series co-added to the accelerations; "
                          "kdk: leapfrog steps (half kick, drift, rebuild, near-field forces, half kick)")
     ap.add_argument("--order", type=int, default=8, help="series order for --stage multipoles / taylor")
+    ap.add_argument("--merge", action="store_true",
+                    help="--stage kdk: gather positions, velocities and accelerations into cell order after each "
+                         "step (the merge step of the paper's pipeline)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -183,7 +186,10 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
         cells.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
     elif not args.no_tune:
         t0 = time.perf_counter()
-        t = cells.autotune(eps, gm, kind, mode, acc, reps=2, cache_path=args.tune_cache)
+        if rho is not None:
+            t = cells.autotune_density(eps, gm, bk, kind, mode, acc, rho, reps=2, cache_path=args.tune_cache)
+        else:
+            t = cells.autotune(eps, gm, kind, mode, acc, reps=2, cache_path=args.tune_cache)
         log(f"tuning ({time.perf_counter() - t0:.1f} s): {t.as_dict()}")
     step_forces()
     nf.sync()
@@ -311,6 +317,9 @@ def run_taylor(args, nf, torch, gen, w, pos, boxes, acc):
     ncomp = (p + 1) * (p + 2) * (p + 3) // 6
     T = torch.from_numpy(gen.taylor_coefficients(nc, p, seed=41, amp=1e-3)).cuda()
     acc.zero_()
+    ms_input_order = _time_calls(args, torch, nf, lambda: cells.taylor_forces(p, T, acc))
+    # the paper keeps particles cell by cell (the merge step): the same evaluation on arrays in cell order
+    cells.reorder([pos, acc])
     ms = _time_calls(args, torch, nf, lambda: cells.taylor_forces(p, T, acc))
     occupied = sum(int((np.bincount(_cells_of(b), minlength=b.K ** 3) > 0).sum()) for b in w.boxes)
     # positions and permutation read, accelerations read and written, coefficients of occupied cells read
@@ -321,7 +330,9 @@ def run_taylor(args, nf, torch, gen, w, pos, boxes, acc):
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"{args.workload}: {w.description}", "n": n, "cells": nc,
-                       "occupied_cells": occupied, "order": p, "components": ncomp},
+                       "occupied_cells": occupied, "order": p, "components": ncomp,
+                       "particle_order": "cell order (after abacus_nf_reorder)"},
+            "ms_input_order": ms_input_order, "particles_per_s_input_order": n / (ms_input_order / 1e3),
             "roofline": _roofline(nbytes, flops, ms, "k_taylor")}
 
 
@@ -340,7 +351,12 @@ def run_kdk(args, nf, torch, w, pos, boxes, eps, gm, acc):
     cells.forces(eps, gm, kind, mode, out=acc)
     dt = cells.timestep(vel, acc, 0.25)
     pairs = cells.interactions()
-    ms = _time_calls(args, torch, nf, lambda: cells.kdk_step(dt, eps, gm, pos, vel, acc, kind, mode))
+    def step():
+        cells.kdk_step(dt, eps, gm, pos, vel, acc, kind, mode)
+        if args.merge:
+            cells.reorder([pos, vel, acc])
+
+    ms = _time_calls(args, torch, nf, step)
     probe = torch.empty_like(vel)
     kick_ms = _time_calls(args, torch, nf, lambda: cells.kick(dt, acc, probe))
     drift_ms = _time_calls(args, torch, nf, lambda: cells.drift([0.0] * len(boxes), probe, pos))
@@ -351,6 +367,7 @@ def run_kdk(args, nf, torch, w, pos, boxes, eps, gm, acc):
             "data": "synthetic",
             "config": {"workload": f"{args.workload}: {w.description}", "n": n, "boxes": len(boxes),
                        "kind": args.kind.split(",")[0], "mode": args.mode.split(",")[0], "dt": dt,
+                       "merge_each_step": bool(args.merge),
                        "interactions_per_step_at_start": pairs, "tuning": cells.get_tuning().as_dict()},
             "interactions_per_s_at_start": pairs / (ms / 1e3),
             "kick": {"ms": kick_ms, "GB/s": stream_bytes / (kick_ms / 1e3) / 1e9,

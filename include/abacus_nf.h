@@ -165,7 +165,7 @@ int abacus_nf_forces_density(abacus_nf_cells cells, const double *eps, abacus_nf
  *          box, (cx*K + cy)*K + cz within a box); every cell is written.
  * Sums are FP64 in a fixed order (deterministic): the sorted particles are cut
  * into units of 1024 slots; a cell that spans several units gets the partial
- * moments of its units added in unit order.  The first call on a handle (or one
+ * moments of its units added in a fixed order.  The first call on a handle (or one
  * with a higher order or a larger batch) allocates the partials buffer
  * (2 x units x components doubles); later calls allocate nothing.
  */
@@ -240,6 +240,22 @@ int abacus_nf_timestep(abacus_nf_cells cells, const float *vel, const float *acc
  */
 int abacus_nf_kdk_step(abacus_nf_cells cells, const double *dt, const double *eps, abacus_nf_kind kind,
                        const double *gm, abacus_nf_sum mode, float *pos, float *vel, float *acc, void *hip_stream);
+
+/*
+ * abacus_nf_reorder -- the merge step (Table "tbl:timing" "Merge New Particles":
+ * particles are kept cell by cell): gather the caller's per-particle arrays into
+ * the sorted order of the last build, in place, so that slot s becomes input
+ * index s.  The handle's permutation becomes the identity; its cells stay valid
+ * for the reordered positions, so every per-particle array of the simulation
+ * (positions included) must be passed, each once.  Later forces, Taylor, kick,
+ * drift and timestep calls then touch those arrays nearly sequentially.
+ *   vec3    host array of n_vec3 (0..64) distinct device float32 [n_total][3]
+ *           pointers (positions, velocities, accelerations, ...).
+ *   ids     optional device int64 [n_total] (particle identities), or NULL.
+ * The first call (or one with a larger batch) allocates n_total x 12 bytes of
+ * scratch; device-to-device copies move the gathered arrays back.
+ */
+int abacus_nf_reorder(abacus_nf_cells cells, float *const *vec3, int32_t n_vec3, int64_t *ids, void *hip_stream);
 
 /*
  * abacus_nf_sync -- wait for the stream, then return (and clear) the first
@@ -321,6 +337,15 @@ int abacus_nf_get_tuning(abacus_nf_cells cells, abacus_nf_tuning *tuning);
 int abacus_nf_autotune(abacus_nf_cells cells, const double *eps, abacus_nf_kind kind, const double *gm,
                        abacus_nf_sum mode, float *acc, void *hip_stream, int32_t reps,
                        const char *cache_path, abacus_nf_tuning *out);
+
+/*
+ * abacus_nf_autotune_density -- the same search for the force pass with the
+ * fused density estimate (abacus_nf_forces_density; b, acc and rho as there),
+ * cached under its own key.
+ */
+int abacus_nf_autotune_density(abacus_nf_cells cells, const double *eps, abacus_nf_kind kind, const double *gm,
+                               abacus_nf_sum mode, const double *b, float *acc, float *rho, void *hip_stream,
+                               int32_t reps, const char *cache_path, abacus_nf_tuning *out);
 
 /*
  * Per-stage timing with HIP events recorded on the caller's stream around the

@@ -68,6 +68,7 @@ def library():
         "abacus_nf_multipoles": [vp, i32, ctypes.POINTER(d), vp, vp],
         "abacus_nf_taylor_forces": [vp, i32, vp, vp, vp],
         "abacus_nf_kick": [vp, ctypes.POINTER(d), vp, vp, vp],
+        "abacus_nf_reorder": [vp, ctypes.POINTER(vp), i32, vp, vp],
         "abacus_nf_drift": [vp, ctypes.POINTER(d), vp, vp, vp],
         "abacus_nf_timestep": [vp, vp, vp, d, ctypes.POINTER(d), vp],
         "abacus_nf_kdk_step": [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d),
@@ -81,6 +82,8 @@ def library():
         "abacus_nf_get_tuning": [vp, ctypes.POINTER(Tuning)],
         "abacus_nf_autotune": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int, vp, vp, i32,
                                ctypes.c_char_p, ctypes.POINTER(Tuning)],
+        "abacus_nf_autotune_density": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int,
+                                       ctypes.POINTER(d), vp, vp, vp, i32, ctypes.c_char_p, ctypes.POINTER(Tuning)],
         "abacus_nf_set_timing": [vp, i32],
         "abacus_nf_last_times": [vp, ctypes.POINTER(ctypes.c_float)],
         "abacus_nf_version": [],
@@ -251,6 +254,20 @@ class Cells:
         _check(rc, "abacus_nf_timestep")
         return list(out)
 
+    def reorder(self, arrays, ids=None, stream=None):
+        """abacus_nf_reorder: gather the [N,3] float32 arrays (positions included) and optional int64 ids
+        into the cell order of the last build, in place."""
+        import torch
+        ptrs = (ctypes.c_void_p * max(1, len(arrays)))(*[self._vec3(t, "array").value for t in arrays])
+        if ids is not None and not (ids.is_cuda and ids.dtype == torch.int64 and ids.shape == (self.n_total,)
+                                    and ids.is_contiguous()):
+            raise ValueError("ids must be a contiguous int64 [N] GPU tensor")
+        rc = library().abacus_nf_reorder(self._h, ptrs, len(arrays),
+                                         ctypes.c_void_p(ids.data_ptr() if ids is not None and ids.numel() else None),
+                                         ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_reorder")
+        return arrays
+
     def kdk_step(self, dt: Sequence[float], eps: Sequence[float], gm: Sequence[float], pos, vel, acc,
                  kind: int = SPLINE, mode: int = SUM_COMP32, stream=None):
         """abacus_nf_kdk_step: one leapfrog step (half kick, drift, rebuild, forces, half kick), in place.
@@ -313,6 +330,23 @@ class Cells:
                                           ctypes.c_void_p(_stream_handle(stream)), int(reps),
                                           cache_path.encode() if cache_path else None, ctypes.byref(t))
         _check(rc, "abacus_nf_autotune")
+        return t
+
+    def autotune_density(self, eps, gm, b, kind=SPLINE, mode=SUM_COMP32, out=None, rho=None, reps: int = 2,
+                         cache_path: Optional[str] = None, stream=None) -> Tuning:
+        """abacus_nf_autotune_density: tune the force pass with the fused density estimate."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_total, 3), dtype=torch.float32, device="cuda")
+        if rho is None:
+            rho = torch.empty(self.n_total, dtype=torch.float32, device="cuda")
+        t = Tuning()
+        rc = library().abacus_nf_autotune_density(self._h, _doubles(eps), int(kind), _doubles(gm), int(mode),
+                                                  _doubles(b), ctypes.c_void_p(out.data_ptr() if out.numel() else None),
+                                                  ctypes.c_void_p(rho.data_ptr() if rho.numel() else None),
+                                                  ctypes.c_void_p(_stream_handle(stream)), int(reps),
+                                                  cache_path.encode() if cache_path else None, ctypes.byref(t))
+        _check(rc, "abacus_nf_autotune_density")
         return t
 
     def set_timing(self, on: bool = True):

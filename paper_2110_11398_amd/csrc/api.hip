@@ -43,6 +43,9 @@ struct abacus_nf_cells_s {
     unsigned long long *ts_min = nullptr;   // [n_boxes]
     size_t ts_cap = 0;
     double *ts_partials = nullptr;
+    // merge scratch (n_total x 12 bytes)
+    size_t merge_cap = 0;
+    void *merge_tmp = nullptr;
 
     // force work buffers
     int64_t wcap_cells = -1, wcap_items = -1, wcap_partials = -1, wcap_boxes = -1;
@@ -134,6 +137,9 @@ void free_step_buffers(abacus_nf_cells_s *h) {
     dfree(h->ts_partials);
     h->scap_boxes = -1;
     h->ts_cap = 0;
+    if (h->merge_tmp) hipFree(h->merge_tmp);
+    h->merge_tmp = nullptr;
+    h->merge_cap = 0;
 }
 
 void free_work_buffers(abacus_nf_cells_s *h) {
@@ -462,7 +468,7 @@ int abacus_nf_multipoles(abacus_nf_cells h, int32_t order, const double *mass, d
         if (!dalloc(h->mp_partials, need)) return ABACUS_NF_ENOMEM;
         h->mp_cap = need;
     }
-    hipError_t e = launch_multipoles(h->spos, h->keys, h->d_boxes, h->n_boxes, h->n_total, h->n_cells, order, mass,
+    hipError_t e = launch_multipoles(h->spos, h->keys, h->cell_start, h->d_boxes, h->n_boxes, h->n_total, h->n_cells, order, mass,
                                      h->d_mass, h->mp_partials, out, dev, (hipStream_t)hip_stream);
     return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
@@ -567,6 +573,32 @@ int abacus_nf_timestep(abacus_nf_cells h, const float *vel, const float *acc, do
         dt_out[b] = std::isinf(r) ? r : eta * r;
     }
     return ABACUS_NF_OK;
+}
+
+int abacus_nf_reorder(abacus_nf_cells h, float *const *vec3, int32_t n_vec3, int64_t *ids, void *hip_stream) {
+    if (!h || n_vec3 < 0 || n_vec3 > 64 || (n_vec3 > 0 && !vec3)) return ABACUS_NF_EINVAL;
+    if (!h->built) return ABACUS_NF_ESTATE;
+    if (h->n_total > 0) {
+        for (int k = 0; k < n_vec3; k++) {
+            if (!vec3[k]) return ABACUS_NF_EINVAL;
+            for (int q = 0; q < k; q++)
+                if (vec3[q] == vec3[k]) return ABACUS_NF_EINVAL;   // each array once
+        }
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (dev != h->device) return ABACUS_NF_ESTATE;
+    if (h->n_total == 0) return ABACUS_NF_OK;
+    const size_t need = (size_t)h->n_total * 12;
+    if (h->merge_cap < need) {
+        if (h->merge_tmp) hipFree(h->merge_tmp);
+        h->merge_tmp = nullptr;
+        h->merge_cap = 0;
+        if (!dalloc_bytes(h->merge_tmp, need)) return ABACUS_NF_ENOMEM;
+        h->merge_cap = need;
+    }
+    hipError_t e = launch_reorder(vec3, n_vec3, ids, h->perm, h->n_total, h->merge_tmp, dev, (hipStream_t)hip_stream);
+    return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 
 int abacus_nf_kdk_step(abacus_nf_cells h, const double *dt, const double *eps, abacus_nf_kind kind,

@@ -14,7 +14,7 @@
 
 namespace {
 
-std::string cache_key(abacus_nf_cells h, abacus_nf_kind kind, abacus_nf_sum mode) {
+std::string cache_key(abacus_nf_cells h, abacus_nf_kind kind, abacus_nf_sum mode, bool kde) {
     int dev = 0;
     hipGetDevice(&dev);
     hipDeviceProp_t p;
@@ -29,6 +29,7 @@ std::string cache_key(abacus_nf_cells h, abacus_nf_kind kind, abacus_nf_sum mode
     const int occ_class = per_cell > 0 ? (int)std::floor(std::log2(per_cell) * 2) : -99;
     std::ostringstream k;
     k << name << "|k" << (int)kind << "|m" << (int)mode << "|n" << size_class << "|o" << occ_class;
+    if (kde) k << "|d";
     return k.str();
 }
 
@@ -77,14 +78,23 @@ void write_cache(const char *path, const std::map<std::string, std::vector<long 
 
 }  // namespace
 
-extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
-                                  abacus_nf_sum mode, float *acc, void *hip_stream, int32_t reps,
-                                  const char *cache_path, abacus_nf_tuning *out) {
+namespace {
+
+// One force call of the kind being tuned: the plain force, or the force with the fused density.
+int force_call(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm, abacus_nf_sum mode,
+               const double *kde_b, float *acc, float *rho, void *hip_stream) {
+    return kde_b ? abacus_nf_forces_density(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream)
+                 : abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+}
+
+int tune(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm, abacus_nf_sum mode,
+         const double *kde_b, float *acc, float *rho, void *hip_stream, int32_t reps, const char *cache_path,
+         abacus_nf_tuning *out) {
     if (!h || reps < 1 || reps > 100) return ABACUS_NF_EINVAL;
     abacus_nf_tuning cur;
     int rc = abacus_nf_get_tuning(h, &cur);
     if (rc) return rc;
-    const std::string key = cache_key(h, kind, mode);
+    const std::string key = cache_key(h, kind, mode, kde_b != nullptr);
     if (cache_path) {
         auto m = read_cache(cache_path);
         auto it = m.find(key);
@@ -97,7 +107,7 @@ extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_n
             t.part_sources = (int32_t)it->second[4];
             t.occupancy = (int32_t)it->second[5];
             if (abacus_nf_set_tuning(h, &t) == ABACUS_NF_OK) {
-                rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+                rc = force_call(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream);
                 if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
                 if (rc == ABACUS_NF_OK && out) abacus_nf_get_tuning(h, out);
                 return rc;
@@ -112,11 +122,12 @@ extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_n
     // time one candidate; keeps the fastest in best / best_t
     auto trial = [&](const abacus_nf_tuning &t) -> int {
         if (abacus_nf_set_tuning(h, &t) != ABACUS_NF_OK) return ABACUS_NF_OK;  // invalid combination: skip
-        int r = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);    // warm-up (allocates if needed)
+        int r = force_call(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream);   // warm-up (allocates if needed)
         if (r == ABACUS_NF_OK) r = abacus_nf_sync(hip_stream);
         if (r != ABACUS_NF_OK) return r;
         hipEventRecord(e0, st);
-        for (int q = 0; q < reps && r == ABACUS_NF_OK; q++) r = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+        for (int q = 0; q < reps && r == ABACUS_NF_OK; q++)
+            r = force_call(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream);
         hipEventRecord(e1, st);
         if (r == ABACUS_NF_OK) r = abacus_nf_sync(hip_stream);
         if (r != ABACUS_NF_OK) return r;
@@ -161,7 +172,7 @@ extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_n
         return rc;
     }
     abacus_nf_set_tuning(h, &best_t);
-    rc = abacus_nf_forces(h, eps, kind, gm, mode, acc, hip_stream);
+    rc = force_call(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream);
     if (rc == ABACUS_NF_OK) rc = abacus_nf_sync(hip_stream);
     if (rc != ABACUS_NF_OK) return rc;
     if (cache_path) {
@@ -172,4 +183,20 @@ extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_n
     }
     if (out) abacus_nf_get_tuning(h, out);
     return ABACUS_NF_OK;
+}
+
+}  // namespace
+
+extern "C" int abacus_nf_autotune(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                                  abacus_nf_sum mode, float *acc, void *hip_stream, int32_t reps,
+                                  const char *cache_path, abacus_nf_tuning *out) {
+    return tune(h, eps, kind, gm, mode, nullptr, acc, nullptr, hip_stream, reps, cache_path, out);
+}
+
+extern "C" int abacus_nf_autotune_density(abacus_nf_cells h, const double *eps, abacus_nf_kind kind,
+                                          const double *gm, abacus_nf_sum mode, const double *b, float *acc,
+                                          float *rho, void *hip_stream, int32_t reps, const char *cache_path,
+                                          abacus_nf_tuning *out) {
+    if (!b) return ABACUS_NF_EINVAL;
+    return tune(h, eps, kind, gm, mode, b, acc, rho, hip_stream, reps, cache_path, out);
 }

@@ -697,8 +697,12 @@ typedef void (*ForcesKernel)(KArgs);
 
 template <int KIND, int MODE, int S, int U, bool KDE>
 ForcesKernel pick_occ(int occ) {
-    if constexpr (KDE) {  // density variants: compiler's register budget or 8 waves per SIMD
-        return occ == 8 ? k_forces<KIND, MODE, S, U, 8, true> : k_forces<KIND, MODE, S, U, 0, true>;
+    if constexpr (KDE) {  // density variants: compiler's register budget, 6 or 8 waves per SIMD
+        switch (occ) {
+            case 6: return k_forces<KIND, MODE, S, U, 6, true>;
+            case 8: return k_forces<KIND, MODE, S, U, 8, true>;
+            default: return k_forces<KIND, MODE, S, U, 0, true>;
+        }
     } else {
         switch (occ) {
             case 6: return k_forces<KIND, MODE, S, U, 6, false>;

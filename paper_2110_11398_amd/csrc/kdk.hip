@@ -25,6 +25,11 @@
 // into a per-box minimum (atomic min on the bits of a non-negative double, so
 // exact and order-free) or, for a cell that crosses a unit boundary, writes the
 // unit's head or tail partial for k_ts_combine.
+//
+// Merge (Table "tbl:timing": particles are stored cell by cell): the caller's
+// per-particle arrays can be gathered into the sorted order of the last build,
+// after which the handle's permutation is the identity; later passes then read
+// and write those arrays nearly sequentially.
 #include "nf_internal.h"
 
 namespace anf {
@@ -83,6 +88,26 @@ __global__ __launch_bounds__(256) void k_drift(float *__restrict__ pos, const fl
         if ((double)f >= L) f = 0.0f;
         pos[e] = f;
     }
+}
+
+// Merge: caller arrays gathered into the sorted order (dst[s] = src[perm[s]]), then copied back.
+__global__ __launch_bounds__(256) void k_permute_f32x3(const float *__restrict__ src, float *__restrict__ dst,
+                                                       const int32_t *__restrict__ perm, int64_t n3) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = e / 3;
+        dst[e] = src[3 * (int64_t)perm[s] + (e - 3 * s)];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_permute_i64(const int64_t *__restrict__ src, int64_t *__restrict__ dst,
+                                                     const int32_t *__restrict__ perm, int64_t n) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+        dst[s] = src[perm[s]];
+}
+
+__global__ __launch_bounds__(256) void k_iota_i32(int32_t *__restrict__ p, int64_t n) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+        p[s] = (int32_t)s;
 }
 
 struct TsArgs {
@@ -231,8 +256,8 @@ __global__ __launch_bounds__(64) void k_ts_combine(TsArgs a) {
         double t[kTsVals];
 #pragma unroll
         for (int k = 0; k < kTsVals; k++) t[k] = a.partials[(2 * (u - 1) + 1) * kTsVals + k];
-        for (int64_t v = u; v < n_units; v++) {
-            if (v > u && a.keys[v * kTsUnit] != c) break;
+        const int64_t last = (a.cs[c + 1] - 1) / kTsUnit;   // unit of the cell's last slot
+        for (int64_t v = u; v <= last; v++) {
             const double *h = a.partials + (2 * v) * kTsVals;
 #pragma unroll
             for (int k = 0; k < 4; k++) t[k] += h[k];
@@ -282,6 +307,27 @@ hipError_t launch_drift(float *pos, const float *vel, int64_t n, const BoxDev *b
     return hipGetLastError();
 }
 
+hipError_t launch_reorder(float *const *vec3, int n_vec3, int64_t *ids, int32_t *perm, int64_t n, void *scratch,
+                          int device, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g3 = (unsigned)grid_of(3 * n, 256, device, 32), g1 = (unsigned)grid_of(n, 256, device, 32);
+    hipError_t e;
+    for (int k = 0; k < n_vec3; k++) {
+        float *tmp = (float *)scratch;
+        hipLaunchKernelGGL(k_permute_f32x3, dim3(g3), dim3(256), 0, st, vec3[k], tmp, perm, 3 * n);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(vec3[k], tmp, (size_t)n * 12, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+    }
+    if (ids) {
+        int64_t *tmp = (int64_t *)scratch;
+        hipLaunchKernelGGL(k_permute_i64, dim3(g1), dim3(256), 0, st, ids, tmp, perm, n);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(ids, tmp, (size_t)n * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_iota_i32, dim3(g1), dim3(256), 0, st, perm, n);
+    return hipGetLastError();
+}
+
 size_t timestep_partial_doubles(int64_t n) {
     const int64_t units = (n + kTsUnit - 1) / kTsUnit;
     return (size_t)(2 * (units > 0 ? units : 1)) * kTsVals;
@@ -309,7 +355,7 @@ hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *ke
     int cus = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
     const int64_t n_units = (n + kTsUnit - 1) / kTsUnit;
-    int64_t grid = std::min<int64_t>(n_units, (int64_t)cus * 16);
+    int64_t grid = std::min<int64_t>(n_units, (int64_t)cus * 32);
     grid = (grid + kQueues - 1) / kQueues * kQueues;
     hipLaunchKernelGGL(k_ts_units, dim3((unsigned)grid), dim3(64), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess || n_units < 2) return e;

@@ -15,11 +15,12 @@
 // (a halo core spans several units, a sparse region packs many cells into one).
 // One wave walks its unit in batches of kMpBatch slots: each lane writes one
 // particle's powers to LDS as x^a y^b (a + b <= p) and w^k, then every lane
-// adds the particles of the batch, in slot order, to the components it owns
-// (component i belongs to lane i % 64) with one FMA each.  At each cell
+// adds the particles of the batch, in slot order, to the components it owns:
+// a 2 x 2 block {x^a y^b, x^a' y^b'} x {w^k, w^k+1} (a + b = a' + b'), four
+// LDS reads for four FMAs.  At each cell
 // boundary the wave writes the cell's moments: directly when the whole cell
 // lies in the unit, else as the unit's head or tail partial, which k_mp_combine
-// adds in unit order.  Empty cells are written as zeros by the unit holding
+// adds in a fixed order.  Empty cells are written as zeros by the unit holding
 // the next occupied cell (or the last unit, for trailing ones).  FP64
 // throughout and fixed orders, so the result does not depend on scheduling.
 #include "nf_internal.h"
@@ -38,24 +39,49 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Exponents of component i in the degree / a-descending / b-descending order.
-__device__ inline void decode_comp(int i, int &a, int &b, int &k) {
-    int n = 0;
-    while ((n + 1) * (n + 2) * (n + 3) / 6 <= i) n++;
-    const int r = i - n * (n + 1) * (n + 2) / 6;
-    int m = 0;  // m = n - a; the entries of degree n with a = n - m start at m (m + 1) / 2
-    while ((m + 1) * (m + 2) / 2 <= r) m++;
-    a = n - m;
-    b = m - (r - m * (m + 1) / 2);
-    k = n - a - b;
-}
-
 // Column of x^a y^b in a power-table row: rows a = 0..P, each b = 0..P-a.
 __host__ __device__ constexpr int xy_index(int P1, int a, int b) { return a * P1 - a * (a - 1) / 2 + b; }
+
+// Position of component (a, b, k) in the degree / a-descending / b-descending order.
+__host__ __device__ constexpr int comp_index(int a, int b, int k) {
+    const int n = a + b + k;
+    return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
+}
+
+// The components are covered by 2 x 2 blocks {x^a y^b, x^a' y^b'} x {w^k, w^k'} with a + b = a' + b' = s
+// and k' = k + 1, so a lane reads at most four powers per particle for up to four products (instead of
+// two reads per product).  Blocks are numbered by s, then by the pair of (a, b) entries (a descending),
+// then by the pair of k; a pair may hold a single entry at the end of its range.
+__host__ __device__ constexpr int mp_blocks(int P) {
+    int n = 0;
+    for (int s = 0; s <= P; s++) n += ((s + 2) / 2) * ((P - s + 2) / 2);
+    return n;
+}
+
+// Block idx: its two (a, b) entries (the second may be absent: b2 < 0) and two k (k2 < 0 if absent).
+__device__ inline void mp_block(int P, int idx, int &a1, int &b1, int &a2, int &b2, int &k1, int &k2) {
+    for (int s = 0; s <= P; s++) {
+        const int nx = (s + 2) / 2, nk = (P - s + 2) / 2;
+        if (idx < nx * nk) {
+            const int j = idx / nk, t = idx % nk;
+            a1 = s - 2 * j;
+            b1 = 2 * j;
+            a2 = 2 * j + 1 <= s ? s - 2 * j - 1 : 0;
+            b2 = 2 * j + 1 <= s ? 2 * j + 1 : -1;
+            k1 = 2 * t;
+            k2 = 2 * t + 1 <= P - s ? 2 * t + 1 : -1;
+            return;
+        }
+        idx -= nx * nk;
+    }
+    a1 = b1 = a2 = k1 = 0;
+    b2 = k2 = -1;
+}
 
 struct MpArgs {
     const float4 *spos;
     const int32_t *keys;   // cell of every slot (sorted)
+    const int32_t *cs;     // first slot of every cell, [n_cells + 1]
     const BoxDev *boxes;
     const double *mass;    // per box (device copy)
     int n_boxes;
@@ -87,19 +113,30 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
     constexpr int NXY = P1 * (P1 + 1) / 2;
     constexpr int ROW = NXY + P1 + 1;   // x^a y^b, then w^k, one pad double
     constexpr int NC = P1 * (P1 + 1) * (P1 + 2) / 6;
-    constexpr int PER = (NC + 63) / 64;
     __shared__ double tab[kMpBatch * ROW];
     const int lane = threadIdx.x;
 
-    int cxy[PER], cz[PER];
+    // this lane's blocks: table columns of the two x^a y^b and two w^k, and the four output components
+    // (-1 where a block is partial, or where the lane has no block)
+    constexpr int NB = mp_blocks(P);
+    constexpr int BPL = (NB + 63) / 64;
+    int cx1[BPL], cx2[BPL], cz1[BPL], cz2[BPL], oc[BPL][4];
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-        const int i = lane + 64 * q;
-        int ea = 0, eb = 0, ek = 0;
-        if (i < NC) decode_comp(i, ea, eb, ek);
-        cxy[q] = xy_index(P1, ea, eb);
-        cz[q] = NXY + ek;
+    for (int r = 0; r < BPL; r++) {
+        const int idx = lane + 64 * r;
+        int a1 = 0, b1 = 0, a2 = 0, b2 = -1, k1 = 0, k2 = -1;
+        if (idx < NB) mp_block(P, idx, a1, b1, a2, b2, k1, k2);
+        const bool has = idx < NB, has_x2 = b2 >= 0, has_k2 = k2 >= 0;
+        cx1[r] = xy_index(P1, a1, b1);
+        cx2[r] = has_x2 ? xy_index(P1, a2, b2) : cx1[r];
+        cz1[r] = NXY + k1;
+        cz2[r] = has_k2 ? NXY + k2 : cz1[r];
+        oc[r][0] = has ? comp_index(a1, b1, k1) : -1;
+        oc[r][1] = has && has_k2 ? comp_index(a1, b1, k2) : -1;
+        oc[r][2] = has && has_x2 ? comp_index(a2, b2, k1) : -1;
+        oc[r][3] = has && has_x2 && has_k2 ? comp_index(a2, b2, k2) : -1;
     }
+    constexpr int NBLK_LAST = NB - 64 * (BPL - 1);   // lanes holding a block in the last round
 
     const int64_t n_units = (a.n + kMpUnit - 1) / kMpUnit;
     const unsigned G = gridDim.x;
@@ -116,19 +153,29 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
         int prev_key = s0 > 0 ? a.keys[s0 - 1] : -1;          // cell of the slot before the unit
         const int after_key = s1 < a.n ? a.keys[s1] : -1;      // cell of the slot after it (-1: none)
         bool started_here = a.keys[s0] != prev_key;            // the current segment's cell began in this unit
-        double acc[PER];
+        double acc[BPL][4];
 #pragma unroll
-        for (int q = 0; q < PER; q++) acc[q] = 0.0;
+        for (int r = 0; r < BPL; r++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[r][q] = 0.0;
 
+        // the next batch's keys and coordinates are loaded while the current one is summed
+        int key_n = lane < kMpBatch && s0 + lane < s1 ? a.keys[s0 + lane] : -2;
+        float4 sp_n = lane < kMpBatch && s0 + lane < s1 ? a.spos[s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int64_t b0 = s0; b0 < s1; b0 += kMpBatch) {
             const int nb = (int)(s1 - b0 < kMpBatch ? s1 - b0 : kMpBatch);
             const bool live = lane < nb;
-            const int key = live ? a.keys[b0 + lane] : -2;
+            const int key = key_n;
+            const float4 sp = sp_n;
+            const int64_t b1 = b0 + kMpBatch;
+            const bool live_n = lane < kMpBatch && b1 + lane < s1;
+            key_n = live_n ? a.keys[b1 + lane] : -2;
+            if (live_n) sp_n = a.spos[b1 + lane];
+            const int first_next = __builtin_amdgcn_readfirstlane(key_n);   // cell of slot b1 when b1 < s1
             int nxt = __shfl_down(key, 1);
-            if (lane == nb - 1) nxt = (b0 + nb < s1) ? a.keys[b0 + nb] : ~key;   // the unit's end closes a segment
+            if (lane == nb - 1) nxt = (b1 < s1) ? first_next : ~key;         // the unit's end closes a segment
             const uint64_t mask = __ballot(live && key != nxt);
             if (live) {
-                const float4 sp = a.spos[b0 + lane];
                 const double x = sp.x, y = sp.y, z = sp.z;
                 double xp[P1], yp[P1];
                 double *row = tab + lane * ROW;
@@ -155,7 +202,14 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
                 for (int t = j; t <= e; t++) {
                     const double *row = tab + t * ROW;
 #pragma unroll
-                    for (int q = 0; q < PER; q++) acc[q] = fma(row[cxy[q]], row[cz[q]], acc[q]);
+                    for (int r = 0; r < BPL; r++) {
+                        if (r == BPL - 1 && lane >= NBLK_LAST) break;   // lanes without a block read nothing
+                        const double x1 = row[cx1[r]], x2 = row[cx2[r]], z1 = row[cz1[r]], z2 = row[cz2[r]];
+                        acc[r][0] = fma(x1, z1, acc[r][0]);
+                        acc[r][1] = fma(x1, z2, acc[r][1]);
+                        acc[r][2] = fma(x2, z1, acc[r][2]);
+                        acc[r][3] = fma(x2, z2, acc[r][3]);
+                    }
                 }
                 if (rest) {
                     // segment of cell c ends at slot b0 + e
@@ -176,10 +230,12 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
                         o = a.partials + (2 * u + (started_here ? 1 : 0)) * NC;
                     }
 #pragma unroll
-                    for (int q = 0; q < PER; q++) {
-                        if (lane + 64 * q < NC) o[lane + 64 * q] = scale * acc[q];
-                        acc[q] = 0.0;
-                    }
+                    for (int r = 0; r < BPL; r++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            if (oc[r][q] >= 0) o[oc[r][q]] = scale * acc[r][q];
+                            acc[r][q] = 0.0;
+                        }
                     prev_key = c;
                     started_here = true;
                 }
@@ -197,7 +253,7 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
 }
 
 // Moments of the cells that cross unit boundaries: the tail partial of the unit where the cell begins,
-// then the head partials of the units it continues into, added in unit order.
+// then the head partials of the units it continues into, added in a fixed order.
 template <int P>
 __global__ __launch_bounds__(64) void k_mp_combine(MpArgs a) {
     constexpr int P1 = P + 1;
@@ -207,12 +263,21 @@ __global__ __launch_bounds__(64) void k_mp_combine(MpArgs a) {
         const int c = a.keys[u * kMpUnit];
         if (a.keys[u * kMpUnit - 1] != c) continue;                          // no cell crosses here
         if (u >= 2 && a.keys[(u - 1) * kMpUnit - 1] == c) continue;          // crossed an earlier boundary
-        int64_t last = u;
-        while (last + 1 < n_units && a.keys[(last + 1) * kMpUnit] == c) last++;
+        const int64_t last = (a.cs[c + 1] - 1) / kMpUnit;                     // unit of the cell's last slot
         const double m = a.n_boxes > 1 ? a.mass[box_of_cell(a.boxes, a.n_boxes, c)] : a.mass[0];
         for (int i = threadIdx.x; i < NC; i += 64) {
-            double t = a.partials[(2 * (u - 1) + 1) * NC + i];
-            for (int64_t v = u; v <= last; v++) t += a.partials[(2 * v) * NC + i];
+            // head partials of units u..last in four interleaved running sums (loads in flight), added in
+            // a fixed order
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+            int64_t v = u;
+            for (; v + 3 <= last; v += 4) {
+                t0 += a.partials[(2 * v) * NC + i];
+                t1 += a.partials[(2 * v + 2) * NC + i];
+                t2 += a.partials[(2 * v + 4) * NC + i];
+                t3 += a.partials[(2 * v + 6) * NC + i];
+            }
+            for (; v <= last; v++) t0 += a.partials[(2 * v) * NC + i];
+            const double t = a.partials[(2 * (u - 1) + 1) * NC + i] + ((t0 + t1) + (t2 + t3));
             a.out[(int64_t)c * NC + i] = m * t;
         }
     }
@@ -245,7 +310,8 @@ size_t multipole_partial_doubles(int64_t n_total, int p) {
     return (size_t)(2 * (units > 0 ? units : 1)) * (size_t)multipole_components(p);
 }
 
-hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const BoxDev *boxes, int n_boxes, int64_t n,
+hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const int32_t *cs, const BoxDev *boxes,
+                             int n_boxes, int64_t n,
                              int64_t n_cells, int p, const double *mass_host, double *mass_dev, double *partials,
                              double *out, int device, hipStream_t st) {
     MpKernel kmain = nullptr, kcomb = nullptr;
@@ -273,6 +339,7 @@ hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const BoxD
     MpArgs a;
     a.spos = spos;
     a.keys = keys;
+    a.cs = cs;
     a.boxes = boxes;
     a.mass = mass_dev;
     a.n_boxes = n_boxes;
@@ -280,8 +347,9 @@ hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const BoxD
     a.n_cells = n_cells;
     a.out = out;
     a.partials = partials;
+    // one unit per block (the dispatcher balances them), a multiple of 8 blocks
     const int64_t n_units = (n + kMpUnit - 1) / kMpUnit;
-    int64_t grid = std::min<int64_t>(n_units, (int64_t)cus * 16);
+    int64_t grid = std::min<int64_t>(n_units, (int64_t)1 << 30);
     grid = (grid + kQueues - 1) / kQueues * kQueues;
     hipLaunchKernelGGL(kmain, dim3((unsigned)grid), dim3(64), 0, st, a);
     hipError_t e = hipGetLastError();

@@ -125,7 +125,8 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 int multipole_components(int p);
 int multipole_max_order();
 size_t multipole_partial_doubles(int64_t n_total, int p);   // unit partials buffer size
-hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const BoxDev *boxes, int n_boxes, int64_t n,
+hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const int32_t *cs, const BoxDev *boxes,
+                             int n_boxes, int64_t n,
                              int64_t n_cells, int p, const double *mass_host, double *mass_dev, double *partials,
                              double *out, int device, hipStream_t st);
 
@@ -180,6 +181,8 @@ hipError_t launch_kick(float *vel, const float *acc, int64_t n, const BoxDev *bo
                        int device, hipStream_t st);
 hipError_t launch_drift(float *pos, const float *vel, int64_t n, const BoxDev *boxes, int n_boxes, const double *dt,
                         int device, hipStream_t st);
+hipError_t launch_reorder(float *const *vec3, int n_vec3, int64_t *ids, int32_t *perm, int64_t n, void *scratch,
+                          int device, hipStream_t st);
 size_t timestep_partial_doubles(int64_t n);
 hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *keys, const int32_t *perm,
                            const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, double *partials,

@@ -8,14 +8,13 @@
 //     Phi = sum_{a+b+k <= p} T^(a,b,k) u^a v^b w^k,
 // the far field is -grad_x Phi = -(K/L) grad_u Phi, added to acc.
 //
-// Work is cut by particle, not by cell: a wave takes 64 consecutive slots of
-// the cell-sorted layout, so every wave carries the same work whatever the
+// Work is cut by particle, not by cell: a wave owns a contiguous run of slots
+// of the cell-sorted layout, so every wave carries the same work whatever the
 // occupancy of the cells (a halo core spans many waves, a sparse region packs
-// several cells into one).  The coefficients of the contiguous range of cells
-// the 64 slots cover are staged in LDS (kTyCells cells at a time) and each lane
-// reads its own cell's block.  Waves on one XCD take one contiguous run of
-// slot batches, so neighbouring batches that share a cell's coefficients share
-// that XCD's L2.
+// several cells into one).  It walks the run in steps of up to 64 slots that
+// cover at most kCells cells, whose coefficients are staged in LDS; each lane
+// reads its own cell's block.  Waves on one XCD take adjacent runs, so a cell
+// whose particles straddle two runs is read from that XCD's L2.
 //
 // Per particle: for every column (b, k) the polynomial P_bk(u) =
 // sum_a T^(a,b,k) u^a and its derivative come from one Horner pass, then
@@ -55,85 +54,104 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// -grad_(u,v,w) of the order-P series with coefficients T at (u, v, w), added to (gx, gy, gz) with the sign
+// of +grad (the caller subtracts).
 template <int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 9 ? 2 : 4, 8))) void k_taylor(TyArgs a) {
+__device__ __forceinline__ void taylor_gradient(const double *__restrict__ T, double u, double v, double w,
+                                                double &gx, double &gy, double &gz) {
+    double pv[P + 1], pw[P + 1];
+    pv[0] = pw[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= P; q++) {
+        pv[q] = pv[q - 1] * v;
+        pw[q] = pw[q - 1] * w;
+    }
+#pragma unroll
+    for (int b = 0; b <= P; b++) {
+#pragma unroll
+        for (int k = 0; k + b <= P; k++) {
+            // Horner over a = top..0 for the value and the derivative of P_bk(u)
+            const int top = P - b - k;
+            double val = T[comp_index(top, b, k)];
+            double der = 0.0;
+#pragma unroll
+            for (int aa = top - 1; aa >= 0; aa--) {
+                der = der * u + val;
+                val = val * u + T[comp_index(aa, b, k)];
+            }
+            const double vw = pv[b] * pw[k];
+            gx += der * vw;
+            if (b > 0) gy += val * (b * pv[b - 1]) * pw[k];
+            if (k > 0) gz += val * pv[b] * (k * pw[k - 1]);
+            // keep each column's reads next to their use (no hoisting of all of them)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 9 ? 2 : 4, 8))) void k_taylor(TyArgs a, const double *__restrict__ taylor) {
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
     constexpr int kCells = kTyStageBytes / (NC * 8) > 0 ? kTyStageBytes / (NC * 8) : 1;
     __shared__ double tc[kCells * NC];
     const int lane = threadIdx.x;
-    // XCD-aware contiguous chunks: block i runs on XCD i % 8; the blocks of one XCD take adjacent chunks
-    const int64_t n_batches = (a.n + 63) >> 6;
+    // XCD-aware contiguous chunks of slots: block i runs on XCD i % 8; the blocks of one XCD take adjacent chunks
     const unsigned G = gridDim.x;
     const unsigned per_xcd = G / kQueues;
     const unsigned vb = (blockIdx.x % kQueues) * per_xcd + blockIdx.x / kQueues;
-    const int64_t chunk = (n_batches + G - 1) / G;
-    const int64_t b_begin = (int64_t)vb * chunk;
-    const int64_t b_end = b_begin + chunk < n_batches ? b_begin + chunk : n_batches;
-    for (int64_t bt = b_begin; bt < b_end; bt++) {
-        const int64_t slot = bt * 64 + lane;
-        const bool live = slot < a.n;
-        const int key = live ? a.keys[slot] : -1;
-        const int c_lo = __builtin_amdgcn_readfirstlane(key);       // lane 0 is always live
-        const int64_t last = (bt * 64 + 64 < a.n ? bt * 64 + 64 : a.n) - 1;
-        const int c_hi = a.keys[last];
-        double u = 0.0, v = 0.0, w = 0.0, s = 0.0;
+    const int64_t chunk = ((a.n + G - 1) / G + 63) / 64 * 64;
+    const int64_t s_begin = (int64_t)vb * chunk;
+    const int64_t s_end = s_begin + chunk < a.n ? s_begin + chunk : a.n;
+    // Steps of up to 64 slots that cover at most kCells cells: every lane of a step evaluates with the
+    // staged coefficients of its own cell, and the next step starts at the first slot not taken.
+    for (int64_t s = s_begin; s < s_end;) {
+        const int64_t slot = s + lane;
+        const bool in_range = slot < s_end;
+        const int key = in_range ? a.keys[slot] : 0x7fffffff;
+        const int c_lo = __builtin_amdgcn_readfirstlane(key);       // lane 0 is always in range
+        const bool live = key - c_lo < kCells;                       // keys are sorted: a prefix of lanes
+        const int taken = __builtin_popcountll(__ballot(live));
+        const int c_hi = __builtin_amdgcn_readlane(key, taken - 1);
+        double u = 0.0, v = 0.0, w = 0.0, sc = 0.0;
         if (live) {
             const float4 sp = a.spos[slot];
             u = sp.x;
             v = sp.y;
             w = sp.z;
             const int bi = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, key) : 0;
-            s = a.boxes[bi].s;
+            sc = a.boxes[bi].s;
         }
+        const int nv = (c_hi - c_lo + 1) * NC;
+        // stage the covered cells' coefficients: every load is issued before the first LDS store, so the
+        // step waits for one memory latency, not one per 64 coefficients
+        constexpr int kIters = (kCells * NC + 63) / 64;
+        const double *src = taylor + (int64_t)c_lo * NC;
+        double stage[kIters];
+#pragma unroll
+        for (int it = 0; it < kIters; it++) {
+            const int i = lane + 64 * it;
+            stage[it] = i < nv ? src[i] : 0.0;
+        }
+        wave_sync();
+#pragma unroll
+        for (int it = 0; it < kIters; it++) {
+            const int i = lane + 64 * it;
+            if (i < nv) tc[i] = stage[it];
+        }
+        wave_sync();
         double gx = 0.0, gy = 0.0, gz = 0.0;
-        for (int c0 = c_lo; c0 <= c_hi; c0 += kCells) {
-            const int nc = c_hi - c0 + 1 < kCells ? c_hi - c0 + 1 : kCells;
-            wave_sync();
-            const double *src = a.taylor + (int64_t)c0 * NC;
-            for (int i = lane; i < nc * NC; i += 64) tc[i] = src[i];
-            wave_sync();
-            if (live && key >= c0 && key < c0 + nc) {
-                const double *T = tc + (key - c0) * NC;
-                double pv[P + 1], pw[P + 1];
-                pv[0] = pw[0] = 1.0;
-#pragma unroll
-                for (int q = 1; q <= P; q++) {
-                    pv[q] = pv[q - 1] * v;
-                    pw[q] = pw[q - 1] * w;
-                }
-#pragma unroll
-                for (int b = 0; b <= P; b++) {
-#pragma unroll
-                    for (int k = 0; k + b <= P; k++) {
-                        // Horner over a = top..0 for the value and the derivative of P_bk(u)
-                        const int top = P - b - k;
-                        double val = T[comp_index(top, b, k)];
-                        double der = 0.0;
-#pragma unroll
-                        for (int aa = top - 1; aa >= 0; aa--) {
-                            der = der * u + val;
-                            val = val * u + T[comp_index(aa, b, k)];
-                        }
-                        const double vw = pv[b] * pw[k];
-                        gx += der * vw;
-                        if (b > 0) gy += val * (b * pv[b - 1]) * pw[k];
-                        if (k > 0) gz += val * pv[b] * (k * pw[k - 1]);
-                        // keep each column's LDS reads next to their use (no hoisting of all of them)
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                }
-            }
-        }
         if (live) {
+            taylor_gradient<P>(tc + (key - c_lo) * NC, u, v, w, gx, gy, gz);
             float *o = a.acc + 3 * (int64_t)a.perm[slot];
-            o[0] = (float)((double)o[0] - s * gx);
-            o[1] = (float)((double)o[1] - s * gy);
-            o[2] = (float)((double)o[2] - s * gz);
+            o[0] = (float)((double)o[0] - sc * gx);
+            o[1] = (float)((double)o[1] - sc * gy);
+            o[2] = (float)((double)o[2] - sc * gz);
         }
+        s += taken;
     }
 }
 
-typedef void (*TyKernel)(TyArgs);
+typedef void (*TyKernel)(TyArgs, const double *);
 
 template <int P>
 TyKernel pick_taylor(int p) {
@@ -165,12 +183,12 @@ hipError_t launch_taylor(const float4 *spos, const int32_t *keys, const int32_t 
     a.acc = acc;
     int cus = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
-    // a multiple of 8 blocks (one share per XCD), at most one 64-slot batch per block
+    // a multiple of 8 blocks (one share per XCD), at least 64 slots per block
     const int64_t n_batches = (n + 63) / 64;
-    int64_t grid = (int64_t)cus * 16;
+    int64_t grid = (int64_t)cus * 20;
     if (grid > n_batches) grid = n_batches;
     grid = (grid + kQueues - 1) / kQueues * kQueues;
-    hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(64), 0, st, a, taylor);
     return hipGetLastError();
 }
 

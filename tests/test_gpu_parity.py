@@ -905,3 +905,39 @@ def test_kdk_loop_with_adaptive_step_conserves_momentum(nf):
     print(f"momentum drift {dv:.3e} of sum|v| {scale:.3e}", flush=True)
     assert scale > 0 and dv <= 1e-4 * scale
     c.free()
+
+
+def test_reorder_merges_arrays_into_cell_order(nf, tiny):
+    """After the merge, every array is the old one gathered by the permutation, the handle's permutation is
+    the identity, and forces / Taylor on the reordered arrays equal the earlier results gathered the same way
+    (bit for bit: the cells, slot order and sums are unchanged)."""
+    b, _ = tiny
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    perm = c.copy(nf.ARRAY_PERM).cpu().numpy().astype(np.int64)
+    pos = torch.from_numpy(b.pos.copy()).cuda()
+    vel = torch.from_numpy(np.random.default_rng(3).standard_normal((b.n, 3)).astype(np.float32)).cuda()
+    ids = torch.arange(b.n, dtype=torch.int64, device="cuda") * 7 + 1
+    a_before = c.forces([b.eps], [b.gm], SPLINE, 1).cpu().numpy()
+    T = torch.from_numpy(gen.taylor_coefficients(b.K ** 3, 8, seed=5, amp=1e-3)).cuda()
+    t_before = torch.zeros((b.n, 3), dtype=torch.float32, device="cuda")
+    c.taylor_forces(8, T, t_before)
+    t_before = t_before.cpu().numpy()
+    v_before = vel.cpu().numpy()
+    c.reorder([pos, vel], ids)
+    assert np.array_equal(pos.cpu().numpy(), b.pos[perm])
+    assert np.array_equal(vel.cpu().numpy(), v_before[perm])
+    assert np.array_equal(ids.cpu().numpy(), perm * 7 + 1)
+    assert np.array_equal(c.copy(nf.ARRAY_PERM).cpu().numpy(), np.arange(b.n))
+    a_after = c.forces([b.eps], [b.gm], SPLINE, 1).cpu().numpy()
+    assert np.array_equal(a_after, a_before[perm])
+    t_after = torch.zeros((b.n, 3), dtype=torch.float32, device="cuda")
+    c.taylor_forces(8, T, t_after)
+    assert np.array_equal(t_after.cpu().numpy(), t_before[perm])
+    # a fresh build of the merged positions keeps the same slots (the sort is stable)
+    c2 = nf.build_cells(pos, [(b.n, b.box, b.K)], 2)
+    assert np.array_equal(c2.copy(nf.ARRAY_PERM).cpu().numpy(), np.arange(b.n))
+    nf.sync()
+    with pytest.raises(nf.NearFieldError):
+        c.reorder([pos, pos])
+    c.free()
+    c2.free()
