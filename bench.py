@@ -62,20 +62,27 @@ def oracle_sample(boxes, kind, target_s, threads, m_fixed=0):
     from workloads.gen import sample_sinks
     b = boxes[0]
     m = m_fixed if m_fixed > 0 else 256
-    t0 = time.perf_counter()
-    sinks = sample_sinks(b.n, m, 99)
-    ref, pairs = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sinks, threads=threads,
-                               return_pairs=True)
-    dt = time.perf_counter() - t0
-    if m_fixed <= 0 and dt < target_s / 3:
-        m = int(min(b.n, max(m, m * target_s / max(dt, 1e-3))))
+    while True:
+        # grow the sample (at most 20x per round) until it takes about target_s: the oracle's per-call
+        # binning of all N particles makes the first, small samples look more expensive per sink
         t0 = time.perf_counter()
         sinks = sample_sinks(b.n, m, 99)
         ref, pairs = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sinks, threads=threads,
                                    return_pairs=True)
         dt = time.perf_counter() - t0
+        if m_fixed > 0 or dt >= target_s / 2 or m >= b.n:
+            break
+        m = int(min(b.n, m * min(20.0, max(2.0, target_s / max(dt, 1e-3)))))
     base = {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"{m} sinks drawn without replacement (seed 99) of box 0; {pairs} FP64 pairs in {dt:.2f} s"}
+    # the same oracle on one core, on a tenth of the sample (a reference point for the thread scaling)
+    m1 = max(16, m // 10)
+    s1 = sample_sinks(b.n, m1, 99)
+    t0 = time.perf_counter()
+    _, p1 = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=s1, threads=1, return_pairs=True)
+    d1 = time.perf_counter() - t0
+    base["single_core"] = {"value": p1 / d1, "unit": "interactions/s", "cores": 1,
+                           "sample": f"{m1} sinks (seed 99); {p1} FP64 pairs in {d1:.2f} s"}
     return base, sinks, ref
 
 
@@ -166,7 +173,9 @@ def main():
                 if kind not in samples:
                     samples[kind] = oracle_sample(w.boxes, kind, args.cpu_seconds, threads, args.err_sinks)
                 base, sinks, ref = samples[kind]
-                line["cpu_baseline"] = base
+                line["cpu_baseline"] = dict(base)
+                # full step on the oracle, extrapolated from its measured rate (not run)
+                line["cpu_baseline"]["extrapolated_full_step_s"] = line["config"]["interactions_per_step"] / base["value"]
                 med, p99 = frac_errors(acc[:w.boxes[0].n].cpu().numpy(), sinks, ref)
                 line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, len(sinks)
             print(json.dumps(line), flush=True)
@@ -259,6 +268,7 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
                       "interactions_per_step": interactions, "tuning": tuning, "hip_graph": bool(args.graph),
                       "density": bool(args.density)},
            "particle_updates_per_s": w.n_total / step_s,
+           "particle_updates_per_s_forces_only": w.n_total / ((stage_ms[1] + stage_ms[2] + stage_ms[3]) / 1e3),
            "stages_ms": {"build_cells": stage_ms[0], "work_list": stage_ms[1], "forces_kernel": stage_ms[2],
                          "finalize": stage_ms[3]},
            "roofline": roofline}
