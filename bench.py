@@ -105,6 +105,8 @@ def main():
                     help="fixed size of the oracle sample (default: sized to about --cpu-seconds)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--f64-out", action="store_true",
+                    help="also report the errors of the FP64 output (abacus_nf_forces_f64) on the oracle sample")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2110_11398_amd", "tuning_cache.json"),
                     help="autotuner cache (JSON); the tuning for this device/kind/mode/size class is looked up "
                          "there and searched (then recorded) if missing")
@@ -178,6 +180,13 @@ def main():
                 line["cpu_baseline"]["extrapolated_full_step_s"] = line["config"]["interactions_per_step"] / base["value"]
                 med, p99 = frac_errors(acc[:w.boxes[0].n].cpu().numpy(), sinks, ref)
                 line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, len(sinks)
+                if args.f64_out:
+                    # the same forces with FP64 output (no final FP32 rounding), an untimed extra call
+                    cells = nf.build_cells(pos, boxes, 2)
+                    a64 = cells.forces_f64(eps, gm, KINDS[kname], MODES[mname])
+                    med, p99 = frac_errors(a64[:w.boxes[0].n].cpu().numpy(), sinks, ref)
+                    line["median_frac_err_f64_out"], line["p99_frac_err_f64_out"] = med, p99
+                    cells.free()
             print(json.dumps(line), flush=True)
 
 

@@ -149,6 +149,17 @@ int abacus_nf_forces_density(abacus_nf_cells cells, const double *eps, abacus_nf
                              abacus_nf_sum mode, const double *b, float *acc, float *rho, void *hip_stream);
 
 /*
+ * abacus_nf_forces_f64 -- the same accelerations written in FP64, without the
+ * final rounding to FP32 (for precision studies: the method's accuracy target
+ * is a median fractional error of 1e-5, and the FP32 output alone contributes
+ * up to 6e-8).  In FP32 mode the FP32 sums are converted exactly.
+ *   acc    device float64 [n_total][3], input order.
+ *   other arguments, errors and allocation as for abacus_nf_forces.
+ */
+int abacus_nf_forces_f64(abacus_nf_cells cells, const double *eps, abacus_nf_kind kind, const double *gm,
+                         abacus_nf_sum mode, double *acc, void *hip_stream);
+
+/*
  * abacus_nf_multipoles -- multipole moments of the mass in every cell (Sec. 3.1:
  * the far-field Taylor coefficients are built from the cells' multipole moments;
  * AbacusSummit uses order p = 8), computed from the handle's cell-relative

@@ -65,6 +65,7 @@ def library():
         "abacus_nf_forces": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int, vp, vp],
         "abacus_nf_forces_density": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int,
                                      ctypes.POINTER(d), vp, vp, vp],
+        "abacus_nf_forces_f64": [vp, ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d), ctypes.c_int, vp, vp],
         "abacus_nf_multipoles": [vp, i32, ctypes.POINTER(d), vp, vp],
         "abacus_nf_taylor_forces": [vp, i32, vp, vp, vp],
         "abacus_nf_kick": [vp, ctypes.POINTER(d), vp, vp, vp],
@@ -170,6 +171,20 @@ class Cells:
                                         ctypes.c_void_p(out.data_ptr() if out.numel() else None),
                                         ctypes.c_void_p(_stream_handle(stream)))
         _check(rc, "abacus_nf_forces")
+        return out
+
+    def forces_f64(self, eps: Sequence[float], gm: Sequence[float], kind: int = SPLINE, mode: int = SUM_COMP32,
+                   out=None, stream=None):
+        """abacus_nf_forces_f64 into out (float64 [N,3] device tensor, allocated if None)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_total, 3), dtype=torch.float64, device="cuda")
+        if not (out.is_cuda and out.dtype == torch.float64 and out.shape == (self.n_total, 3) and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 [N,3] GPU tensor")
+        rc = library().abacus_nf_forces_f64(self._h, _doubles(eps), int(kind), _doubles(gm), int(mode),
+                                            ctypes.c_void_p(out.data_ptr() if out.numel() else None),
+                                            ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_forces_f64")
         return out
 
     def forces_density(self, eps: Sequence[float], gm: Sequence[float], b: Sequence[float], kind: int = SPLINE,

@@ -324,7 +324,7 @@ int abacus_nf_build_cells(const float *pos, int64_t n_total, const abacus_nf_box
 }
 
 static int check_force_args(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
-                            abacus_nf_sum mode, float *acc) {
+                            abacus_nf_sum mode, const void *acc) {
     if (!h || !eps || !gm) return ABACUS_NF_EINVAL;
     if (kind != ABACUS_NF_SPLINE && kind != ABACUS_NF_PLUMMER) return ABACUS_NF_EINVAL;
     if (mode != ABACUS_NF_SUM_FP32 && mode != ABACUS_NF_SUM_COMP32 && mode != ABACUS_NF_SUM_FP64)
@@ -400,8 +400,9 @@ static ForcesArgs make_args(abacus_nf_cells_s *h, abacus_nf_kind kind, abacus_nf
 }
 
 static int forces_impl(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
-                       abacus_nf_sum mode, const double *kde_b, float *acc, float *rho, void *hip_stream) {
-    int rc = check_force_args(h, eps, kind, gm, mode, acc);
+                       abacus_nf_sum mode, const double *kde_b, float *acc, float *rho, void *hip_stream,
+                       double *acc64 = nullptr) {
+    int rc = check_force_args(h, eps, kind, gm, mode, acc64 ? (const void *)acc64 : (const void *)acc);
     if (rc != ABACUS_NF_OK) return rc;
     if (kde_b) {
         if (h->n_total > 0 && !rho) return ABACUS_NF_EINVAL;
@@ -419,6 +420,7 @@ static int forces_impl(abacus_nf_cells h, const double *eps, abacus_nf_kind kind
     hipStream_t st = (hipStream_t)hip_stream;
     if (h->n_total == 0) return ABACUS_NF_OK;
     ForcesArgs a = make_args(h, kind, mode, acc, err);
+    a.acc64 = acc64;
     a.rho = kde_b ? rho : nullptr;
     const int key[8] = {(int)kind, (int)mode, h->tune.sinks_per_lane, h->tune.unroll, h->tune.chunk,
                         h->tune.waves_per_cu, dev * 2 + (kde_b ? 1 : 0), h->tune.occupancy};
@@ -450,6 +452,11 @@ int abacus_nf_forces_density(abacus_nf_cells h, const double *eps, abacus_nf_kin
                              abacus_nf_sum mode, const double *b, float *acc, float *rho, void *hip_stream) {
     if (!b) return ABACUS_NF_EINVAL;
     return forces_impl(h, eps, kind, gm, mode, b, acc, rho, hip_stream);
+}
+
+int abacus_nf_forces_f64(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double *gm,
+                         abacus_nf_sum mode, double *acc, void *hip_stream) {
+    return forces_impl(h, eps, kind, gm, mode, nullptr, nullptr, nullptr, hip_stream, acc);
 }
 
 int abacus_nf_multipoles(abacus_nf_cells h, int32_t order, const double *mass, double *out, void *hip_stream) {

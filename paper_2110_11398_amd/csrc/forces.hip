@@ -311,6 +311,7 @@ struct KArgs {
     const int64_t *cell_pbase;
     double *partials;
     float *acc;
+    double *acc64;  // FP64 accelerations instead of acc when not null
     float *rho;
     int R;
     int chunk;      // sources per LDS chunk
@@ -618,9 +619,8 @@ void k_forces(KArgs a) {
                 const int base = (g * L * S + s) * NC;
                 if (!split) {
                     const int64_t i = a.perm[cs0 + t0 + idx];
-                    float *out = a.acc + 3 * i;
                     for (int d = 0; d < NC; d++) {
-                        float v;
+                        double v;   // the value before its (optional) rounding to FP32
                         if constexpr (MODE == ABACUS_NF_SUM_FP32) {
                             float t = 0.f;
                             for (int q = 0; q < L; q++) t += redf[base + q * S * NC + d];
@@ -628,10 +628,11 @@ void k_forces(KArgs a) {
                         } else {
                             double t = 0.0;
                             for (int q = 0; q < L; q++) t += red[base + q * S * NC + d];
-                            v = (float)(d < 3 ? t * F.scale : t);
+                            v = d < 3 ? t * F.scale : t;
                         }
-                        if (d < 3) out[d] = v;
-                        else a.rho[i] = v;
+                        if (d == 3) a.rho[i] = (float)v;
+                        else if (a.acc64) a.acc64[3 * i + d] = v;
+                        else a.acc[3 * i + d] = (float)v;
                     }
                 } else {
                     double *out = a.partials + (int64_t)NC * (a.cell_pbase[c] + (int64_t)part * nc + t0 + idx);
@@ -663,7 +664,7 @@ __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ 
                                                   const double *__restrict__ partials,
                                                   const BoxDev *__restrict__ boxes, int n_boxes,
                                                   const ForceBox *__restrict__ fbox, float *__restrict__ acc,
-                                                  float *__restrict__ rho, int64_t n) {
+                                                  double *__restrict__ acc64, float *__restrict__ rho, int64_t n) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n || ws->overflow) return;
     const int32_t c = keys[s];
@@ -676,7 +677,7 @@ __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ 
     const ForceBox F = fbox[b];
     const int64_t i = perm[s];
     for (int d = 0; d < NC; d++) {
-        float v;
+        double v;   // the value before its (optional) rounding to FP32
         if constexpr (MODE == ABACUS_NF_SUM_FP32) {
             float t = 0.f;
             for (int p = 0; p < P; p++) t += (float)partials[NC * (base + (int64_t)p * nc) + d];
@@ -684,10 +685,11 @@ __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ 
         } else {
             double t = 0.0;
             for (int p = 0; p < P; p++) t += partials[NC * (base + (int64_t)p * nc) + d];
-            v = (float)(d < 3 ? t * F.scale : t);
+            v = d < 3 ? t * F.scale : t;
         }
-        if (d < 3) acc[3 * i + d] = v;
-        else rho[i] = v;
+        if (d == 3) rho[i] = (float)v;
+        else if (acc64) acc64[3 * i + d] = v;
+        else acc[3 * i + d] = (float)v;
     }
 }
 
@@ -856,6 +858,7 @@ hipError_t launch_forces(const ForcesArgs &a, hipStream_t st) {
     k.cell_pbase = a.cell_pbase;
     k.partials = a.partials;
     k.acc = a.acc;
+    k.acc64 = a.acc64;
     k.rho = a.rho;
     k.R = a.R;
     k.chunk = a.tune.chunk;
@@ -874,7 +877,8 @@ hipError_t launch_finalize(const ForcesArgs &a, hipStream_t st) {
     auto kfn = f32 ? (kde ? k_finalize<ABACUS_NF_SUM_FP32, 4> : k_finalize<ABACUS_NF_SUM_FP32, 3>)
                    : (kde ? k_finalize<ABACUS_NF_SUM_FP64, 4> : k_finalize<ABACUS_NF_SUM_FP64, 3>);
     hipLaunchKernelGGL(kfn, dim3(gn), dim3(256), 0, st, a.ws, a.partial_capacity, a.keys, a.cell_start, a.perm,
-                       a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.rho, a.n_total);
+                       a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.acc64, a.rho,
+                       a.n_total);
     return hipGetLastError();
 }
 

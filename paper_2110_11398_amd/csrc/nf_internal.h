@@ -158,6 +158,7 @@ struct ForcesArgs {
     double *partials;
     int64_t partial_capacity;
     float *acc;
+    double *acc64;   // FP64 accelerations instead of acc (nullptr: FP32 output)
     float *rho;      // density output (nullptr: forces only)
     int *err;
     abacus_nf_kind kind;

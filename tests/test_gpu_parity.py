@@ -941,3 +941,72 @@ def test_reorder_merges_arrays_into_cell_order(nf, tiny):
         c.reorder([pos, pos])
     c.free()
     c2.free()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_forces_f64_output_is_the_unrounded_value(nf, tiny, mode):
+    """The FP64 output rounds to the FP32 output bit for bit, and is at least as close to the oracle."""
+    b, tref = tiny
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    a32 = c.forces([b.eps], [b.gm], SPLINE, mode).cpu().numpy()
+    a64 = c.forces_f64([b.eps], [b.gm], SPLINE, mode).cpu().numpy()
+    nf.sync()
+    assert a64.dtype == np.float64
+    assert np.array_equal(a64.astype(np.float32), a32)
+    ref, _, mag = tref[SPLINE]
+    med32, _ = check(a32.astype(np.float64), ref, mag, f"fp32 out mode={mode}")
+    med64, _ = check(a64, ref, mag, f"fp64 out mode={mode}")
+    assert med64 <= med32 * 1.0001
+    c.free()
+
+
+def test_forces_f64_output_split_cells(nf):
+    """A cell heavy enough to be split into source parts goes through the FP64 finalize path."""
+    rng = np.random.default_rng(12)
+    p = np.concatenate([0.31 + 0.004 * rng.standard_normal((20000, 3)), rng.random((3000, 3))]) % 1.0
+    p = p.astype(np.float32)
+    c = nf.build_cells(torch.from_numpy(p).cuda(), [(len(p), 1.0, 8)], 2)
+    c.set_tuning(part_sources=4096)
+    eps, gm = (1.0 / 8) / 40, 1.0 / len(p)
+    a32 = c.forces([eps], [gm], SPLINE, 1).cpu().numpy()
+    a64 = c.forces_f64([eps], [gm], SPLINE, 1).cpu().numpy()
+    nf.sync()
+    assert np.array_equal(a64.astype(np.float32), a32)
+    c.free()
+
+
+def test_kdk_steps_captured_in_a_hip_graph(nf, tiny):
+    """One leapfrog step (uploads, kicks, drift, rebuild, forces) captured once and replayed three times gives
+    bit for bit the state of three eager steps; eager work and synchronisations run between the replays."""
+    b, _ = tiny
+    dt = 0.02
+    vel0 = (0.05 * np.random.default_rng(8).standard_normal((b.n, 3))).astype(np.float32)
+    boxes = [(b.n, b.box, b.K)]
+
+    def fresh():
+        p = torch.from_numpy(b.pos.copy()).cuda()
+        v = torch.from_numpy(vel0.copy()).cuda()
+        c = nf.build_cells(p, boxes, 2)
+        a = c.forces([b.eps], [b.gm], SPLINE, 1)
+        c.kick([0.0], a, v)       # allocates the step buffers (v + a * 0 leaves v unchanged)
+        nf.sync()
+        return c, p, v, a
+
+    c1, p1, v1, a1 = fresh()
+    for _ in range(3):
+        c1.kdk_step([dt], [b.eps], [b.gm], p1, v1, a1, SPLINE, 1)
+    nf.sync()
+    c2, p2, v2, a2 = fresh()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        c2.kdk_step([dt], [b.eps], [b.gm], p2, v2, a2, SPLINE, 1)
+    for r in range(3):
+        junk = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
+        assert junk == 1000.0
+        g.replay()
+        torch.cuda.synchronize()
+        nf.sync()
+    assert torch.equal(p1, p2) and torch.equal(v1, v2) and torch.equal(a1, a2)
+    c1.free()
+    c2.free()
