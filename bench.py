@@ -57,40 +57,62 @@ def traffic_from_profile(workload: str, kind: str, mode: str, tuning: dict):
 
 
 def oracle_sample(boxes, kind, target_s, threads, m_fixed=0):
-    """Time the FP64 oracle on a bounded sample of sinks of box 0 (about target_s seconds, or m_fixed sinks)."""
+    """Time the FP64 oracle on a bounded sample of sinks (about target_s seconds, or m_fixed sinks in all).
+
+    One box: sinks drawn from it. Several boxes: the sample is spread over up to 8 boxes (the first ones, equal
+    shares), each evaluated with its own softening and mass. Returns the baseline record and a list of
+    (global index of the sampled sinks, FP64 reference accelerations)."""
     import oracle
     from workloads.gen import sample_sinks
-    b = boxes[0]
-    m = m_fixed if m_fixed > 0 else 256
+    use = boxes[:min(8, len(boxes))]
+    offs = np.cumsum([0] + [b.n for b in boxes])
+
+    def run(m_total):
+        share = max(1, m_total // len(use))
+        parts, pairs = [], 0
+        for k, b in enumerate(use):
+            sk = sample_sinks(b.n, min(share, b.n), 99 + k)
+            ref, pr = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sk, threads=threads,
+                                    return_pairs=True)
+            parts.append((sk + offs[k], ref))
+            pairs += pr
+        return parts, pairs, sum(len(sk) for sk, _ in parts)
+
+    n_use = sum(b.n for b in use)
+    m = m_fixed if m_fixed > 0 else 256 * len(use)
     while True:
         # grow the sample (at most 20x per round) until it takes about target_s: the oracle's per-call
-        # binning of all N particles makes the first, small samples look more expensive per sink
+        # binning of all particles of a box makes the first, small samples look more expensive per sink
         t0 = time.perf_counter()
-        sinks = sample_sinks(b.n, m, 99)
-        ref, pairs = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=sinks, threads=threads,
-                                   return_pairs=True)
+        parts, pairs, got = run(m)
         dt = time.perf_counter() - t0
-        if m_fixed > 0 or dt >= target_s / 2 or m >= b.n:
+        if m_fixed > 0 or dt >= target_s / 2 or got >= n_use or m >= n_use:
             break
-        m = int(min(b.n, m * min(20.0, max(2.0, target_s / max(dt, 1e-3)))))
+        m = int(min(n_use, m * min(20.0, max(2.0, target_s / max(dt, 1e-3)))))
+    where = "box 0" if len(use) == 1 else f"boxes 0-{len(use) - 1} (equal shares, seeds 99+box)"
     base = {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-            "sample": f"{m} sinks drawn without replacement (seed 99) of box 0; {pairs} FP64 pairs in {dt:.2f} s"}
-    # the same oracle on one core, on a tenth of the sample (a reference point for the thread scaling)
-    m1 = max(16, m // 10)
+            "sample": f"{got} sinks drawn without replacement (seed 99) of {where}; {pairs} FP64 pairs in {dt:.2f} s"}
+    # the same oracle on one core, on a tenth of the sample of box 0 (a reference point for the thread scaling)
+    b = boxes[0]
+    m1 = max(16, min(b.n, got // 10))
     s1 = sample_sinks(b.n, m1, 99)
     t0 = time.perf_counter()
     _, p1 = oracle.forces(b.pos, b.box, b.K, 2, b.eps, kind, b.gm, sinks=s1, threads=1, return_pairs=True)
     d1 = time.perf_counter() - t0
     base["single_core"] = {"value": p1 / d1, "unit": "interactions/s", "cores": 1,
-                           "sample": f"{m1} sinks (seed 99); {p1} FP64 pairs in {d1:.2f} s"}
-    return base, sinks, ref
+                           "sample": f"{m1} sinks of box 0 (seed 99); {p1} FP64 pairs in {d1:.2f} s"}
+    return base, parts
 
 
-def frac_errors(acc_box0, sinks, ref):
-    a = acc_box0[sinks].astype(np.float64)
-    na = np.linalg.norm(ref, axis=1)
-    fe = np.linalg.norm(a - ref, axis=1)[na > 0] / na[na > 0]
-    return float(np.median(fe)), float(np.percentile(fe, 99))
+def frac_errors(acc_all, parts):
+    """Median and 99th percentile of |a - a_ref| / |a_ref| over the sampled sinks of all sampled boxes."""
+    fes = []
+    for idx, ref in parts:
+        a = acc_all[idx].astype(np.float64)
+        na = np.linalg.norm(ref, axis=1)
+        fes.append(np.linalg.norm(a - ref, axis=1)[na > 0] / na[na > 0])
+    fe = np.concatenate(fes)
+    return float(np.median(fe)), float(np.percentile(fe, 99)), int(sum(len(i) for i, _ in parts))
 
 
 def main():
@@ -174,17 +196,17 @@ def main():
                 kind = KINDS[kname]
                 if kind not in samples:
                     samples[kind] = oracle_sample(w.boxes, kind, args.cpu_seconds, threads, args.err_sinks)
-                base, sinks, ref = samples[kind]
+                base, parts = samples[kind]
                 line["cpu_baseline"] = dict(base)
                 # full step on the oracle, extrapolated from its measured rate (not run)
                 line["cpu_baseline"]["extrapolated_full_step_s"] = line["config"]["interactions_per_step"] / base["value"]
-                med, p99 = frac_errors(acc[:w.boxes[0].n].cpu().numpy(), sinks, ref)
-                line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, len(sinks)
+                med, p99, ns = frac_errors(acc.cpu().numpy(), parts)
+                line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, ns
                 if args.f64_out:
                     # the same forces with FP64 output (no final FP32 rounding), an untimed extra call
                     cells = nf.build_cells(pos, boxes, 2)
                     a64 = cells.forces_f64(eps, gm, KINDS[kname], MODES[mname])
-                    med, p99 = frac_errors(a64[:w.boxes[0].n].cpu().numpy(), sinks, ref)
+                    med, p99, _ = frac_errors(a64.cpu().numpy(), parts)
                     line["median_frac_err_f64_out"], line["p99_frac_err_f64_out"] = med, p99
                     cells.free()
             print(json.dumps(line), flush=True)

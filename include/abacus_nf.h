@@ -12,7 +12,7 @@
  *     a_i = G*m * sum_j d_ij * g(|d_ij|),   d_ij = x_j' - x_i,
  *
  * with g the softened inverse cube: the spline law that is exactly Newtonian
- * beyond the softening length (Sec. 2.4 "Code Parameters", Sec. 5.2
+ * beyond the softening length (Sec. 2.5 "Code Parameters", Sec. 5.2
  * "Accuracy") or Plummer's g = (r^2 + eps^2)^(-3/2) (Sec. 5.2).  The spline
  * interior used here is the cubic force polynomial whose value, slope and
  * curvature match 1/r^2 at r = eps: |F| eps^2 = 10u - 15u^2 + 6u^3, u = r/eps.
@@ -52,7 +52,7 @@ extern "C" {
 #define ABACUS_NF_ENONFINITE -5 /* a position was NaN or infinite                 */
 #define ABACUS_NF_ESTATE -6     /* handle used in the wrong state                 */
 
-/* Softening law (Sec. 2.4, Sec. 5.2). */
+/* Softening law (Sec. 2.5, Sec. 5.2). */
 typedef enum {
     ABACUS_NF_SPLINE = 0,  /* exactly 1/r^2 beyond eps; cubic force polynomial inside */
     ABACUS_NF_PLUMMER = 1  /* potential -1/sqrt(r^2 + eps^2)                          */
@@ -109,7 +109,7 @@ int abacus_nf_build_cells(const float *pos, int64_t n_total, const abacus_nf_box
 
 /*
  * abacus_nf_forces -- near-field accelerations of every particle (Sec. 3.1
- * direct sum; softening of Sec. 2.4 / Sec. 5.2).
+ * direct sum; softening of Sec. 2.5 / Sec. 5.2).
  *
  *   cells  a handle filled by abacus_nf_build_cells on the same stream.
  *   eps    host double [n_boxes]: softening length of each box in the box's
@@ -132,7 +132,7 @@ int abacus_nf_forces(abacus_nf_cells cells, const double *eps, abacus_nf_kind ki
 
 /*
  * abacus_nf_forces_density -- the same accelerations plus the kernel density
- * estimate computed in the same near-field pass (Sec. 3.4 "Halo Finding":
+ * estimate computed in the same near-field pass (Sec. 3.3 "Halo Finding":
  * weight 1 - r^2/b^2 for pairs closer than b).  For every particle
  *     rho_i = sum over its near field (self pair included) of max(0, 1 - r^2/b^2),
  * a dimensionless count-weighted density (multiply by m / volume as needed).
@@ -201,7 +201,7 @@ int abacus_nf_taylor_forces(abacus_nf_cells cells, int32_t order, const double *
                             void *hip_stream);
 
 /*
- * Leapfrog time stepping (Sec. 2 "time stepping": second-order kick-drift-kick
+ * Leapfrog time stepping (Sec. 2.5, time stepping: second-order kick-drift-kick
  * leapfrog with one global step per simulation; Sec. 3.1: singlestep kicks,
  * drifts and moves particles to their new cells before the next force
  * evaluation).  Positions, velocities and accelerations are device float32
@@ -224,7 +224,7 @@ int abacus_nf_kick(abacus_nf_cells cells, const double *dt, const float *acc, fl
 int abacus_nf_drift(abacus_nf_cells cells, const double *dt, const float *vel, float *pos, void *hip_stream);
 
 /*
- * abacus_nf_timestep -- the step-size criterion (Sec. 2 "time stepping"):
+ * abacus_nf_timestep -- the step-size criterion (Sec. 2.5, time stepping):
  *     dt_b = eta * min over the cells c of box b of sigma_c / max_{j in c} |a_j|,
  * sigma_c^2 = (1/n_c) sum_{j in c} |v_j - mean_c(v)|^2 (all three components).
  * Cells with fewer than two particles or no nonzero acceleration do not

@@ -6,8 +6,8 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * ``oracle_nf.c`` (built into ``liboracle_nf.so``): the cell-walk FP64 oracle
   written from Sec. 3.1 of the paper (near field = cells within R, explicit
   periodic images, direct sum), the spline and Plummer softening laws of
-  Sec. 2.4 / Sec. 5.2, the cell rule, and an exact pair counter.
-* the kernel density estimate fused into the same pass (Sec. 3.4), weight
+  Sec. 2.5 / Sec. 5.2, the cell rule, and an exact pair counter.
+* the kernel density estimate fused into the same pass (Sec. 3.3), weight
   max(0, 1 - r^2/b^2) over the near field, self pair included (a reading).
 * cell multipoles (Sec. 3.1, order p = 8): complete Cartesian moments about
   each cell centre, positions in cell widths (a reading of the basis).

@@ -1,6 +1,6 @@
 """Leapfrog time stepping and the cell timestep criterion (test infrastructure only).
 
-Sec. 2 (time stepping): particles advance with second-order leapfrog in its
+Sec. 2.5, time stepping: particles advance with second-order leapfrog in its
 kick-drift-kick form, one global step size for every particle; the step size
 is the smallest, over the cells, of the velocity dispersion of the cell divided
 by the largest acceleration in it, times eta (0.25 in the simulations).  The

@@ -17,7 +17,7 @@
  *
  * with g the softened inverse cube (attractive: d points from i to j).
  *
- * Softening laws (Sec. 2.4 "Code Parameters" and Sec. 5.2 "Accuracy"):
+ * Softening laws (Sec. 2.5 "Code Parameters" and Sec. 5.2 "Accuracy"):
  *   kind 0, spline : g = 1/r^3 for r >= eps (exact Newtonian force beyond a
  *                    finite radius); inside, the force is the cubic
  *                    polynomial in r that matches the value, slope and
@@ -34,7 +34,7 @@
  * multiply-add; build with -ffp-contract=off).  Linear cell index
  * (cx*K + cy)*K + cz.
  *
- * Kernel density estimate (Sec. 3.4 "Halo Finding"): computed in the same
+ * Kernel density estimate (Sec. 3.3 "Halo Finding"): computed in the same
  * near-field pass, the density of particle i is the sum over its near field
  * of the weight max(0, 1 - r^2/b^2) (b is a fixed radius; the paper takes 40%
  * of the mean interparticle spacing).  The self pair is included (weight 1):
@@ -253,7 +253,7 @@ int oracle_nf_count_pairs(const float *pos, int64_t n, double L, int K, int R, i
 }
 
 /*
- * Kernel density estimate over the near field (Sec. 3.4): for each sink,
+ * Kernel density estimate over the near field (Sec. 3.3): for each sink,
  * rho = sum over (j, image) in NF(i) of max(0, 1 - r^2/b^2), self pair included.
  *   rho [nsinks] float64 out, in the order of `sinks` (all particles if NULL).
  * b must be positive; pairs beyond R cells are not visited, so b should not

@@ -1,7 +1,7 @@
 // Near-field force: device work list and the persistent pairwise kernel.
 //
 // The operation is the direct sum of Sec. 3.1 (near field = cells within R,
-// explicit periodic images) with the spline or Plummer softening of Sec. 2.4
+// explicit periodic images) with the spline or Plummer softening of Sec. 2.5
 // and Sec. 5.2.  The paper runs it as CUDA kernels on host-packaged work units
 // ("Index Near Force Pencils", "spatially compact GPU work units", Sec. 4.3 and
 // Sec. 4.5).  Here the work list is built on the device and one persistent

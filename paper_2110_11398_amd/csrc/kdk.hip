@@ -1,6 +1,6 @@
 // Leapfrog time stepping: kick, drift and the cell timestep criterion.
 //
-// Sec. 2 (time stepping): particles advance with second-order leapfrog in its
+// Sec. 2.5, time stepping: particles advance with second-order leapfrog in its
 // kick-drift-kick form with one global step per simulation; the step is eta
 // times the smallest, over the cells, of the velocity dispersion of a cell
 // over the largest acceleration in it.  Sec. 3.1: singlestep kicks, drifts and

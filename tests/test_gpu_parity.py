@@ -423,7 +423,7 @@ def test_bad_tuning_is_rejected(nf):
     c.free()
 
 
-# ---------------------------------------------------------------- fused kernel density estimate (Sec. 3.4)
+# ---------------------------------------------------------------- fused kernel density estimate (Sec. 3.3)
 
 def run_density(nf, pos_np, boxes, eps, gm, bs, kind=SPLINE, mode=1, tuning=None):
     pos = torch.from_numpy(np.ascontiguousarray(pos_np, dtype=np.float32)).cuda()
@@ -558,6 +558,24 @@ def _mp_cell_of(n_in_cell, K=8, seed=0):
     cell = np.floor(bg / w).astype(int)
     bg = bg[~np.all(cell == [3, 4, 5], axis=1)][:K ** 3]
     return np.concatenate([inner, bg]).astype(np.float32)
+
+
+def test_multipoles_sparse_cells(nf):
+    """Fewer than 16 particles per cell on average (the narrow power-table path), with a dense clump so that
+    cells also cross unit boundaries."""
+    rng = np.random.default_rng(13)
+    K = 14
+    p = np.concatenate([rng.random((9000, 3)), 0.7 + 0.01 * rng.standard_normal((3000, 3))]) % 1.0
+    p = p.astype(np.float32)
+    assert len(p) < 16 * K ** 3
+    c = nf.build_cells(torch.from_numpy(p).cuda(), [(len(p), 1.0, K)], 2)
+    got = c.multipoles(8, [0.5]).cpu().numpy()
+    nf.sync()
+    ref = oracle.multipoles(p, 1.0, K, 8, 0.5)
+    counts = np.bincount(oracle.bin_cells(p, 1.0, K), minlength=K ** 3)
+    assert counts.max() > 1024
+    _mp_check(got, ref, counts, 0.5, "multipoles sparse")
+    c.free()
 
 
 @pytest.mark.parametrize("n_in_cell", [2047, 2048, 2049, 4096, 6001])

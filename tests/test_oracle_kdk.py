@@ -1,5 +1,5 @@
 """Pins of the leapfrog / timestep oracle (oracle/kdk.py) against closed forms, invariants of the
-integrator and planted mistakes (Sec. 2 time stepping, Sec. 3.1 kick / drift / rebin)."""
+integrator and planted mistakes (Sec. 2.5, time stepping, Sec. 3.1 kick / drift / rebin)."""
 import os
 import types
 

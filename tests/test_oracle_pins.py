@@ -255,7 +255,7 @@ def test_empty_and_invalid_arguments(orc):
         orc.forces(np.zeros((4, 3), np.float32), 1.0, 5, 2, 0.0)     # eps <= 0
 
 
-# ---------------------------------------------------------------- kernel density estimate (Sec. 3.4)
+# ---------------------------------------------------------------- kernel density estimate (Sec. 3.3)
 
 @pytest.mark.parametrize("n,K", [(2, 5), (300, 5), (2000, 7)])
 def test_density_matches_brute_force(orc, n, K):

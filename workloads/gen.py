@@ -3,7 +3,7 @@
 The paper measures on its own simulation (base_c000_ph000 at z=90.5, nearly
 uniform, and at z=0.105, highly clustered; Table "tbl:timing").  Those snapshots
 are not available, so these generators stand in for them with the same shapes:
-about 67 particles per cell at R=2 (Sec. 2.4 "Code Parameters"), near-uniform
+about 67 particles per cell at R=2 (Sec. 2.5 "Code Parameters"), near-uniform
 early times, and halo-dominated late times where the near field dominates the
 runtime (Sec. 4.3, Fig. "timing_overiew").
 
