@@ -343,7 +343,8 @@ int abacus_nf_get_tuning(abacus_nf_cells cells, abacus_nf_tuning *tuning);
  * in, and recorded to, that JSON file under a key made of the device name,
  * kind, mode and a size class of the batch.  acc receives the forces of the
  * last run.  The chosen tuning is stored in the handle and, if out is not
- * NULL, returned.
+ * NULL, returned.  With the environment variable ABACUS_NF_AUTOTUNE_LOG=1 the
+ * time of every candidate is printed to stderr.
  */
 int abacus_nf_autotune(abacus_nf_cells cells, const double *eps, abacus_nf_kind kind, const double *gm,
                        abacus_nf_sum mode, float *acc, void *hip_stream, int32_t reps,

@@ -2,6 +2,7 @@
 // sharing on the handle's own data and keeps the fastest.  Choices can be
 // cached in a small JSON file keyed by device, kind, mode and a size class.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -120,6 +121,9 @@ int tune(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double
     float best = 1e30f;
     abacus_nf_tuning best_t = cur;
     // time one candidate; keeps the fastest in best / best_t
+    // ABACUS_NF_AUTOTUNE_LOG=1 prints every candidate's time to stderr
+    const char *log_env = getenv("ABACUS_NF_AUTOTUNE_LOG");
+    const bool log_trials = log_env && log_env[0] == '1';
     auto trial = [&](const abacus_nf_tuning &t) -> int {
         if (abacus_nf_set_tuning(h, &t) != ABACUS_NF_OK) return ABACUS_NF_OK;  // invalid combination: skip
         int r = force_call(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream);   // warm-up (allocates if needed)
@@ -133,6 +137,9 @@ int tune(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double
         if (r != ABACUS_NF_OK) return r;
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
+        if (log_trials)   // one line per candidate, so long searches show progress
+            fprintf(stderr, "[abacus_nf autotune] S=%d U=%d chunk=%d max_lanes=%d occupancy=%d: %.3f ms\n",
+                    t.sinks_per_lane, t.unroll, t.chunk, t.max_lanes, t.occupancy, ms / reps);
         if (ms < best) {
             best = ms;
             best_t = t;

@@ -375,20 +375,50 @@ __device__ __forceinline__ void accumulate(const float4 (&p)[U], const float (&x
                                            double (&dxs)[S], double (&dys)[S], double (&dzs)[S], float (&rh)[S]) {
 #pragma unroll
     for (int u = 0; u < U; u++) {
+        float dx[S], dy[S], dz[S], r2[S], gg[S];
+        if constexpr (KIND == ABACUS_NF_SPLINE) {
+            // Newtonian regime test for the whole wave: when no lane has a pair closer than eps for this
+            // source, g = r^-3 exactly and the softening polynomial is skipped (one wave-uniform branch;
+            // close pairs are rare at the softening lengths of the method)
+            bool near = false;
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                dx[s] = p[u].x - xi[s];
+                dy[s] = p[u].y - yi[s];
+                dz[s] = p[u].z - zi[s];
+                r2[s] = __builtin_fmaf(dx[s], dx[s], __builtin_fmaf(dy[s], dy[s], __builtin_fmaf(dz[s], dz[s], kTiny)));
+                near = near || r2[s] < e2;
+            }
+            if (__builtin_amdgcn_ballot_w64(near)) {
+#pragma unroll
+                for (int s = 0; s < S; s++) gg[s] = pair_g<KIND>(dx[s], dy[s], dz[s], c0, c1, c2, e2, r2[s]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    const float ri = __builtin_amdgcn_rsqf(r2[s]);
+                    gg[s] = (ri * ri) * ri;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                dx[s] = p[u].x - xi[s];
+                dy[s] = p[u].y - yi[s];
+                dz[s] = p[u].z - zi[s];
+                gg[s] = pair_g<KIND>(dx[s], dy[s], dz[s], c0, c1, c2, e2, r2[s]);
+            }
+        }
 #pragma unroll
         for (int s = 0; s < S; s++) {
-            const float dx = p[u].x - xi[s], dy = p[u].y - yi[s], dz = p[u].z - zi[s];
-            float r2;
-            const float gg = pair_g<KIND>(dx, dy, dz, c0, c1, c2, e2, r2);
-            if constexpr (KDE) rh[s] += fmaxf(__builtin_fmaf(-r2, ib2, kc), 0.f);
+            if constexpr (KDE) rh[s] += fmaxf(__builtin_fmaf(-r2[s], ib2, kc), 0.f);
             if constexpr (MODE == ABACUS_NF_SUM_FP64) {
-                dxs[s] += (double)(dx * gg);
-                dys[s] += (double)(dy * gg);
-                dzs[s] += (double)(dz * gg);
+                dxs[s] += (double)(dx[s] * gg[s]);
+                dys[s] += (double)(dy[s] * gg[s]);
+                dzs[s] += (double)(dz[s] * gg[s]);
             } else {
-                ax[s] = __builtin_fmaf(dx, gg, ax[s]);
-                ay[s] = __builtin_fmaf(dy, gg, ay[s]);
-                az[s] = __builtin_fmaf(dz, gg, az[s]);
+                ax[s] = __builtin_fmaf(dx[s], gg[s], ax[s]);
+                ay[s] = __builtin_fmaf(dy[s], gg[s], ay[s]);
+                az[s] = __builtin_fmaf(dz[s], gg[s], az[s]);
             }
         }
     }
