@@ -1028,3 +1028,51 @@ def test_kdk_steps_captured_in_a_hip_graph(nf, tiny):
     assert torch.equal(p1, p2) and torch.equal(v1, v2) and torch.equal(a1, a2)
     c1.free()
     c2.free()
+
+
+def test_widening_entries_on_empty_input(nf):
+    """No particles: multipoles are all zero, Taylor / kick / drift / merge do nothing, the step is +inf."""
+    p = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    c = nf.build_cells(p, [(0, 1.0, 5)], 2)
+    M = c.multipoles(8, [1.0]).cpu().numpy()
+    assert M.shape == (125, 165) and np.all(M == 0.0)
+    v = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    a = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    c.taylor_forces(8, torch.zeros((125, 165), dtype=torch.float64, device="cuda"), a)
+    c.kick([0.1], a, v)
+    c.reorder([p, v, a])
+    assert np.isinf(c.timestep(v, a, 0.25)[0])
+    c.kdk_step([0.1], [0.01], [1.0], p, v, a)
+    c.drift([0.1], v, p)
+    nf.sync()
+    c.free()
+
+
+def test_widening_entries_with_an_empty_box_in_the_batch(nf):
+    """A batch whose middle box is empty: its cells' moments are zero, its step is +inf, and the other boxes
+    match the oracle box by box."""
+    rng = np.random.default_rng(17)
+    p1 = rng.random((3000, 3)).astype(np.float32)
+    p3 = (0.5 + 0.1 * rng.standard_normal((2500, 3))).astype(np.float32) % np.float32(1.0)
+    pos = np.concatenate([p1, p3])
+    boxes = [(len(p1), 1.0, 5), (0, 1.0, 6), (len(p3), 1.0, 7)]
+    c = nf.build_cells(torch.from_numpy(pos).cuda(), boxes, 2)
+    M = c.multipoles(4, [0.5, 2.0, 0.25]).cpu().numpy()
+    assert np.all(M[125:125 + 216] == 0.0)
+    for (pb, K, m, base) in ((p1, 5, 0.5, 0), (p3, 7, 0.25, 125 + 216)):
+        ref = oracle.multipoles(pb, 1.0, K, 4, m)
+        counts = np.bincount(oracle.bin_cells(pb, 1.0, K), minlength=K ** 3)
+        _mp_check(M[base:base + K ** 3], ref, counts, m, f"multipoles batch with empty box K={K}")
+    vel = rng.standard_normal(pos.shape).astype(np.float32)
+    acc = rng.standard_normal(pos.shape).astype(np.float32)
+    dt = c.timestep(torch.from_numpy(vel).cuda(), torch.from_numpy(acc).cuda(), 0.25)
+    ref = [okdk.cell_timestep(p1, vel[:3000], acc[:3000], 1.0, 5, 0.25), np.inf,
+           okdk.cell_timestep(p3, vel[3000:], acc[3000:], 1.0, 7, 0.25)]
+    _ts_check(dt, ref, "timestep batch with empty box")
+    v = torch.from_numpy(vel).cuda()
+    c.kick([0.1, 7.0, 0.2], torch.from_numpy(acc).cuda(), v)
+    got = v.cpu().numpy()
+    nf.sync()
+    assert np.array_equal(got[:3000], okdk.kick(vel[:3000], acc[:3000], 0.1))
+    assert np.array_equal(got[3000:], okdk.kick(vel[3000:], acc[3000:], 0.2))
+    c.free()
