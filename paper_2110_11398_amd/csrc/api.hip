@@ -43,6 +43,8 @@ struct abacus_nf_cells_s {
     unsigned long long *ts_min = nullptr;   // [n_boxes]
     size_t ts_cap = 0;
     double *ts_partials = nullptr;
+    int64_t ts_ref_cap = 0;
+    float *ts_ref = nullptr;                // [n_cells][3] reference velocities
     // merge scratch (n_total x 12 bytes)
     size_t merge_cap = 0;
     void *merge_tmp = nullptr;
@@ -135,8 +137,10 @@ void free_step_buffers(abacus_nf_cells_s *h) {
     dfree(h->d_dt);
     dfree(h->ts_min);
     dfree(h->ts_partials);
+    dfree(h->ts_ref);
     h->scap_boxes = -1;
     h->ts_cap = 0;
+    h->ts_ref_cap = 0;
     if (h->merge_tmp) hipFree(h->merge_tmp);
     h->merge_tmp = nullptr;
     h->merge_cap = 0;
@@ -515,6 +519,13 @@ static int ensure_step_buffers(abacus_nf_cells_s *h, bool timestep) {
             if (!dalloc(h->ts_partials, need)) return ABACUS_NF_ENOMEM;
             h->ts_cap = need;
         }
+        const int64_t nref = 3 * std::max<int64_t>(h->n_cells, 1);
+        if (h->ts_ref_cap < nref) {
+            dfree(h->ts_ref);
+            h->ts_ref_cap = 0;
+            if (!dalloc(h->ts_ref, (size_t)nref)) return ABACUS_NF_ENOMEM;
+            h->ts_ref_cap = nref;
+        }
     }
     return ABACUS_NF_OK;
 }
@@ -567,7 +578,7 @@ int abacus_nf_timestep(abacus_nf_cells h, const float *vel, const float *acc, do
     if (rc != ABACUS_NF_OK) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e = launch_timestep(vel, acc, h->keys, h->perm, h->cell_start, h->d_boxes, h->n_boxes, h->n_total,
-                                   h->ts_partials, h->ts_min, dev, st);
+                                   h->n_cells, h->ts_partials, h->ts_ref, h->ts_min, dev, st);
     if (e != hipSuccess) return hip_fail(e);
     std::vector<unsigned long long> bits((size_t)h->n_boxes);
     if (hipMemcpyAsync(bits.data(), h->ts_min, bits.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,

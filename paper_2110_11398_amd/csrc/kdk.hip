@@ -14,7 +14,8 @@
 // stored as 0 if its FP32 rounding reaches L.  Both kernels stream the arrays
 // once (HBM-bound, 36 bytes per particle each).
 //
-// Timestep: per cell, with v_ref the velocity of the cell's first particle and
+// Timestep: per cell, with v_ref the velocity of the cell's first particle (gathered
+// once per cell by k_ts_ref) and
 // d = v - v_ref, the sums S1 = sum d, S2 = sum |d|^2 and A = max |a|^2 give
 // sigma^2 = S2 / n - |S1 / n|^2 (the shift keeps the difference well
 // conditioned when the cell moves in bulk).  Cells with fewer than two
@@ -121,7 +122,25 @@ struct TsArgs {
     int64_t n;
     double *partials;             // [2 per unit][kTsVals]: head, tail
     unsigned long long *dmin;     // [n_boxes] bits of the smallest sigma / |a|max
+    const float *ref;             // [n_cells][3] velocity of each occupied cell's first particle
 };
+
+// Reference velocity of every occupied cell: the velocity of its first sorted particle (read once per cell,
+// so the per-particle pass below has no chain of dependent lookups for it).
+__global__ __launch_bounds__(256) void k_ts_ref(const float *__restrict__ vel, const int32_t *__restrict__ perm,
+                                                const int32_t *__restrict__ cs, int64_t n_cells,
+                                                float *__restrict__ ref) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int s0 = cs[c];
+        if (cs[c + 1] > s0) {
+            const int64_t r = perm[s0];
+            ref[3 * c + 0] = vel[3 * r + 0];
+            ref[3 * c + 1] = vel[3 * r + 1];
+            ref[3 * c + 2] = vel[3 * r + 2];
+        }
+    }
+}
 
 __device__ inline double cell_ratio(const double *t, int n) {
     // sigma / |a|max, or a negative value when the cell does not constrain the step
@@ -155,22 +174,30 @@ __global__ __launch_bounds__(64) void k_ts_units(TsArgs a) {
         const int after = s1 < a.n ? a.keys[s1] : -1;
         double carry[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
         int carry_key = -1;
+        // the next batch's keys and permutation entries are loaded while the current one is reduced
+        int key_n = s0 + lane < s1 ? a.keys[s0 + lane] : -2;
+        int perm_n = s0 + lane < s1 ? a.perm[s0 + lane] : 0;
         for (int64_t b0 = s0; b0 < s1; b0 += 64) {
             const int nb = (int)(s1 - b0 < 64 ? s1 - b0 : 64);
             const bool live = lane < nb;
-            const int key = live ? a.keys[b0 + lane] : -2;
+            const int key = key_n;
+            const int64_t i = perm_n;
+            const int64_t b1 = b0 + 64;
+            const bool live_n = b1 + lane < s1;
+            key_n = live_n ? a.keys[b1 + lane] : -2;
+            perm_n = live_n ? a.perm[b1 + lane] : 0;
+            const int first_next = __builtin_amdgcn_readfirstlane(key_n);   // cell of slot b1 when b1 < s1
             const int prevk = __shfl_up(key, 1);
             int nxt = __shfl_down(key, 1);
-            if (lane == nb - 1) nxt = (b0 + nb < s1) ? a.keys[b0 + nb] : ~key;   // the unit's end closes a segment
+            if (lane == nb - 1) nxt = (b1 < s1) ? first_next : ~key;       // the unit's end closes a segment
             const bool end = live && key != nxt;
             const uint64_t endmask = __ballot(end);
             double x[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if (live) {
-                const int64_t i = a.perm[b0 + lane];
-                const int64_t r = a.perm[a.cs[key]];
-                const double dx = (double)a.vel[3 * i + 0] - (double)a.vel[3 * r + 0];
-                const double dy = (double)a.vel[3 * i + 1] - (double)a.vel[3 * r + 1];
-                const double dz = (double)a.vel[3 * i + 2] - (double)a.vel[3 * r + 2];
+                const float *vr = a.ref + 3 * (int64_t)key;
+                const double dx = (double)a.vel[3 * i + 0] - (double)vr[0];
+                const double dy = (double)a.vel[3 * i + 1] - (double)vr[1];
+                const double dz = (double)a.vel[3 * i + 2] - (double)vr[2];
                 const double ax = a.acc[3 * i + 0], ay = a.acc[3 * i + 1], az = a.acc[3 * i + 2];
                 x[0] = dx;
                 x[1] = dy;
@@ -334,8 +361,8 @@ size_t timestep_partial_doubles(int64_t n) {
 }
 
 hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *keys, const int32_t *perm,
-                           const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, double *partials,
-                           unsigned long long *dmin, int device, hipStream_t st) {
+                           const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, int64_t n_cells,
+                           double *partials, float *ref, unsigned long long *dmin, int device, hipStream_t st) {
     const unsigned long long inf_bits = 0x7FF0000000000000ull;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n_boxes + 255) / 256)), dim3(256), 0, st, dmin,
                        (int64_t)n_boxes, inf_bits);
@@ -352,6 +379,10 @@ hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *ke
     a.n = n;
     a.partials = partials;
     a.dmin = dmin;
+    a.ref = ref;
+    hipLaunchKernelGGL(k_ts_ref, dim3((unsigned)grid_of(n_cells, 256, device, 32)), dim3(256), 0, st, vel, perm, cs,
+                       n_cells, ref);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     int cus = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
     const int64_t n_units = (n + kTsUnit - 1) / kTsUnit;

@@ -186,7 +186,7 @@ hipError_t launch_reorder(float *const *vec3, int n_vec3, int64_t *ids, int32_t 
                           int device, hipStream_t st);
 size_t timestep_partial_doubles(int64_t n);
 hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *keys, const int32_t *perm,
-                           const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, double *partials,
-                           unsigned long long *dmin, int device, hipStream_t st);
+                           const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, int64_t n_cells,
+                           double *partials, float *ref, unsigned long long *dmin, int device, hipStream_t st);
 
 }  // namespace anf
