@@ -101,7 +101,19 @@ def oracle_sample(boxes, kind, target_s, threads, m_fixed=0):
     d1 = time.perf_counter() - t0
     base["single_core"] = {"value": p1 / d1, "unit": "interactions/s", "cores": 1,
                            "sample": f"{m1} sinks of box 0 (seed 99); {p1} FP64 pairs in {d1:.2f} s"}
+    base["cpu_model"] = cpu_model()
     return base, parts
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or an empty string."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def frac_errors(acc_all, parts):
