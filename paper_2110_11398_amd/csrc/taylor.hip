@@ -103,51 +103,84 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 9 ? 2 :
     const int64_t s_begin = (int64_t)vb * chunk;
     const int64_t s_end = s_begin + chunk < a.n ? s_begin + chunk : a.n;
     // Steps of up to 64 slots that cover at most kCells cells: every lane of a step evaluates with the
-    // staged coefficients of its own cell, and the next step starts at the first slot not taken.
-    for (int64_t s = s_begin; s < s_end;) {
-        const int64_t slot = s + lane;
-        const bool in_range = slot < s_end;
-        const int key = in_range ? a.keys[slot] : 0x7fffffff;
-        const int c_lo = __builtin_amdgcn_readfirstlane(key);       // lane 0 is always in range
-        const bool live = key - c_lo < kCells;                       // keys are sorted: a prefix of lanes
-        const int taken = __builtin_popcountll(__ballot(live));
-        const int c_hi = __builtin_amdgcn_readlane(key, taken - 1);
-        double u = 0.0, v = 0.0, w = 0.0, sc = 0.0;
-        if (live) {
-            const float4 sp = a.spos[slot];
-            u = sp.x;
-            v = sp.y;
-            w = sp.z;
-            const int bi = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, key) : 0;
-            sc = a.boxes[bi].s;
-        }
+    // staged coefficients of its own cell, and the next step starts at the first slot not taken.  The walk is
+    // software-pipelined: while a step is evaluated, the next step's coefficients, coordinates and
+    // permutation entries are already in flight, and the keys of the step after it.
+    constexpr int kIters = (kCells * NC + 63) / 64;
+    if (s_begin >= s_end) return;
+    const int kNone = 0x7fffffff;
+    int64_t s = s_begin;
+    int key = s + lane < s_end ? a.keys[s + lane] : kNone;
+    // window of the current step
+    int c_lo = __builtin_amdgcn_readfirstlane(key);                  // lane 0 is always in range
+    bool live = key - c_lo < kCells;                                  // keys are sorted: a prefix of lanes
+    int taken = __builtin_popcountll(__ballot(live));
+    int c_hi = __builtin_amdgcn_readlane(key, taken - 1);
+    double stage[kIters];
+    {
         const int nv = (c_hi - c_lo + 1) * NC;
-        // stage the covered cells' coefficients: every load is issued before the first LDS store, so the
-        // step waits for one memory latency, not one per 64 coefficients
-        constexpr int kIters = (kCells * NC + 63) / 64;
         const double *src = taylor + (int64_t)c_lo * NC;
-        double stage[kIters];
 #pragma unroll
-        for (int it = 0; it < kIters; it++) {
-            const int i = lane + 64 * it;
-            stage[it] = i < nv ? src[i] : 0.0;
-        }
+        for (int it = 0; it < kIters; it++) stage[it] = lane + 64 * it < nv ? src[lane + 64 * it] : 0.0;
+    }
+    float4 sp = live ? a.spos[s + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    int pi = live ? a.perm[s + lane] : 0;
+    int64_t s_next = s + taken;
+    int key_next = s_next + lane < s_end ? a.keys[s_next + lane] : kNone;
+    for (;;) {
+        // the current step's coefficients to LDS
+        const int nv = (c_hi - c_lo + 1) * NC;
         wave_sync();
 #pragma unroll
-        for (int it = 0; it < kIters; it++) {
-            const int i = lane + 64 * it;
-            if (i < nv) tc[i] = stage[it];
-        }
+        for (int it = 0; it < kIters; it++)
+            if (lane + 64 * it < nv) tc[lane + 64 * it] = stage[it];
         wave_sync();
-        double gx = 0.0, gy = 0.0, gz = 0.0;
+        // the next step: its window from the keys already loaded; issue its loads and the keys after it
+        const bool more = s_next < s_end;
+        int c_lo_n = 0, taken_n = 0, c_hi_n = 0, pi_n = 0, key_after = kNone;
+        bool live_n = false;
+        float4 sp_n = make_float4(0.f, 0.f, 0.f, 0.f);
+        int64_t s_after = s_end;
+        if (more) {
+            c_lo_n = __builtin_amdgcn_readfirstlane(key_next);
+            live_n = key_next - c_lo_n < kCells;
+            taken_n = __builtin_popcountll(__ballot(live_n));
+            c_hi_n = __builtin_amdgcn_readlane(key_next, taken_n - 1);
+            const int nv_n = (c_hi_n - c_lo_n + 1) * NC;
+            const double *src = taylor + (int64_t)c_lo_n * NC;
+#pragma unroll
+            for (int it = 0; it < kIters; it++) stage[it] = lane + 64 * it < nv_n ? src[lane + 64 * it] : 0.0;
+            if (live_n) {
+                sp_n = a.spos[s_next + lane];
+                pi_n = a.perm[s_next + lane];
+            }
+            s_after = s_next + taken_n;
+            key_after = s_after + lane < s_end ? a.keys[s_after + lane] : kNone;
+        }
+        // evaluate the current step
         if (live) {
+            const double u = sp.x, v = sp.y, w = sp.z;
+            const int bi = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, key) : 0;
+            const double sc = a.boxes[bi].s;
+            double gx = 0.0, gy = 0.0, gz = 0.0;
             taylor_gradient<P>(tc + (key - c_lo) * NC, u, v, w, gx, gy, gz);
-            float *o = a.acc + 3 * (int64_t)a.perm[slot];
+            float *o = a.acc + 3 * (int64_t)pi;
             o[0] = (float)((double)o[0] - sc * gx);
             o[1] = (float)((double)o[1] - sc * gy);
             o[2] = (float)((double)o[2] - sc * gz);
         }
-        s += taken;
+        if (!more) break;
+        // rotate: the next step becomes the current one
+        s = s_next;
+        key = key_next;
+        c_lo = c_lo_n;
+        live = live_n;
+        taken = taken_n;
+        c_hi = c_hi_n;
+        sp = sp_n;
+        pi = pi_n;
+        s_next = s_after;
+        key_next = key_after;
     }
 }
 
