@@ -348,9 +348,11 @@ static int check_force_args(abacus_nf_cells h, const double *eps, abacus_nf_kind
 static int ensure_work_buffers(abacus_nf_cells_s *h) {
     const int64_t n = std::max<int64_t>(h->n_total, 1);
     const int64_t nc = std::max<int64_t>(h->n_cells, 1);
+    // unsplit items: one tile per non-empty cell, one per 64 sink groups, and at most one more per 11
+    // groups of a cell's rest (its binary cut); split source lists take the rest of the capacity
     const int64_t want_items = h->tune.item_capacity > 0
                                    ? h->tune.item_capacity
-                                   : std::min<int64_t>(INT32_MAX - 1, std::min(n, nc) + n / 16 + (1 << 16));
+                                   : std::min<int64_t>(INT32_MAX - 1, std::min(n, nc) + n / 16 + n / 11 + (1 << 16));
     const int64_t want_partials = 2 * n + (1 << 16);
     if (h->wcap_cells >= nc && h->wcap_items == want_items && h->wcap_partials >= want_partials &&
         h->wcap_boxes >= h->n_boxes)

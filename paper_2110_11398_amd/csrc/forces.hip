@@ -122,9 +122,9 @@ __device__ inline CellPlan plan_cell(int n, int nsrc, int S, int max_lanes, int 
         p.cls = kNumClasses - 1;
         return p;
     }
-    const TileGeom tg = tile_geom(n, S, max_lanes);
-    p.tiles = (n + tg.cap - 1) / tg.cap;
-    const int64_t iters = ((int64_t)nsrc + tg.L - 1) / tg.L;  // source iterations per lane
+    p.tiles = tile_count(n, S, max_lanes);
+    const int L0 = tile_at(n, S, max_lanes, 0).L;               // the heaviest tile: fewest lanes per group
+    const int64_t iters = ((int64_t)nsrc + L0 - 1) / L0;        // source iterations per lane
     int64_t parts = (iters + part_iters - 1) / part_iters;
     if (parts < 1) parts = 1;
     if (parts > nsrc) parts = nsrc > 0 ? nsrc : 1;
@@ -471,10 +471,10 @@ void k_forces(KArgs a) {
         const int cz = lin % K, cy = (lin / K) % K, cx = lin / (K * K);
         const int cs0 = a.cs[c];
         const int nc = a.cs[c + 1] - cs0;
-        const TileGeom tg = tile_geom(nc, S, a.max_lanes);
+        const TileGeom tg = tile_at(nc, S, a.max_lanes, sgpr(it.tile));
         const int L = tg.L, G = tg.G;
-        const int t0 = sgpr(it.tile) * tg.cap;
-        const int nt = min(tg.cap, nc - t0);
+        const int t0 = tg.t0;
+        const int nt = tg.nt;
         const int g = lane / L, sub = lane - g * L;
 
         // sink tile: S sinks per lane, relative to the sink cell centre

@@ -60,24 +60,81 @@ struct WorkState {
     int32_t class_base[kNumClasses];
 };
 
-// Tile geometry of a cell with n sinks: L lanes share each sink group, G
-// groups per wave, S sinks per lane, so one tile holds cap = G * S sinks.
+// Sink tiles of one cell.  The n sinks form g = ceil(n / S) groups of S (one
+// group per lane); a tile of G groups gives each group L = 64 / G lanes (at most
+// max_lanes), which split the sources between them.  Whole tiles of 64 groups
+// (L = 1) come first.  A rest of r < 64 groups is one tile when that tile keeps
+// at least 7/8 of the wave's lanes busy, when L is at its cap, or when r is a
+// power of two; otherwise a tile of the largest power of two k < r groups
+// (L = 64 / k, every lane busy) is cut off and the rest follows the same rule.
+// So every tile but a cell's last fills its wave (e.g. 43 groups: 32 with L = 2,
+// 8 with L = 8, 3 with L = 21), and tile 0 has the fewest lanes per group.
 struct TileGeom {
-    int L, G, cap;
+    int L, G;     // lanes per group, groups (capacity G * S sinks)
+    int t0, nt;   // first sink of the tile within the cell, sinks in the tile
 };
 
-__host__ __device__ inline TileGeom tile_geom(int n, int S, int max_lanes) {
-    TileGeom t;
-    int groups = (n + S - 1) / S;
-    if (groups >= 64 || n <= 0) {
-        t.L = 1;
-    } else {
-        int L = 64 / groups;
-        t.L = L < max_lanes ? L : max_lanes;
+// One tile of a rest of r groups: returns true when it takes the whole rest.
+__host__ __device__ inline bool rest_tile(int r, int max_lanes, int &L, int &G) {
+    int L0 = 64 / r;
+    if (L0 > max_lanes) L0 = max_lanes;
+    const int k = 1 << (31 - __builtin_clz((unsigned)r));   // largest power of two <= r
+    if (k == r || 8 * r * L0 >= 7 * 64 || 64 / k > max_lanes) {
+        L = L0;
+        G = 64 / L0;
+        return true;
     }
-    t.G = 64 / t.L;
-    t.cap = t.G * S;
-    return t;
+    L = 64 / k;
+    G = k;
+    return false;
+}
+
+__host__ __device__ inline int tile_count(int n, int S, int max_lanes) {
+    if (n <= 0) return 0;
+    const int g = (n + S - 1) / S;
+    int count = g / 64, r = g - 64 * (g / 64);
+    while (r > 0) {
+        int L, G;
+        count++;
+        if (rest_tile(r, max_lanes, L, G)) break;
+        r -= G;
+    }
+    return count;
+}
+
+// Tile number `tile` (0 <= tile < tile_count) of a cell with n > 0 sinks.
+__host__ __device__ inline TileGeom tile_at(int n, int S, int max_lanes, int tile) {
+    TileGeom t;
+    const int g = (n + S - 1) / S;
+    const int full = g / 64;
+    if (tile < full) {
+        t.L = 1;
+        t.G = 64;
+        t.t0 = tile * 64 * S;
+        t.nt = n - t.t0 < 64 * S ? n - t.t0 : 64 * S;
+        return t;
+    }
+    int r = g - 64 * full, t0 = full * 64 * S;
+    if (r <= 0) {   // no such tile: an empty one
+        t.L = 1;
+        t.G = 64;
+        t.t0 = n;
+        t.nt = 0;
+        return t;
+    }
+    for (int k = full;; k++) {
+        int L, G;
+        const bool last = rest_tile(r, max_lanes, L, G);
+        if (k == tile || last) {
+            t.L = L;
+            t.G = G;
+            t.t0 = t0;
+            t.nt = last ? n - t0 : G * S;
+            return t;
+        }
+        t0 += G * S;
+        r -= G;
+    }
 }
 
 // Box of particle i: the last box whose offset is <= i (boxes partition the input in order).

@@ -187,6 +187,38 @@ def test_tiling_variants(nf, tiny, tuning):
         c.free()
 
 
+@pytest.fixture(scope="module")
+def cut_cells():
+    """K = 6, each cell holding a count drawn from sizes that exercise every kind of sink-tile cut: a rest that
+    fills its wave in one tile, binary cuts into two or three tiles, whole 64-group tiles plus a rest, one sink."""
+    rng = np.random.default_rng(21)
+    K = 6
+    sizes = np.array([0, 1, 2, 3, 9, 11, 17, 43, 63, 64, 65, 100, 129, 150, 257, 300])
+    counts = rng.choice(sizes, size=K ** 3)
+    g = np.stack(np.meshgrid(np.arange(K), np.arange(K), np.arange(K), indexing="ij"), -1).reshape(-1, 3)
+    cell = np.repeat(g, counts, axis=0)
+    pos = ((cell + rng.random((len(cell), 3))) / K).astype(np.float32) % np.float32(1.0)
+    eps = 0.002
+    ref, pairs, mag = oracle.forces(pos, 1.0, K, 2, eps, SPLINE, 1.0 / len(pos), return_pairs=True, return_mag=True)
+    return pos, K, eps, ref, pairs, mag
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(sinks_per_lane=1, unroll=1, chunk=256, max_lanes=64),
+    dict(sinks_per_lane=2, unroll=2, chunk=256, max_lanes=8),
+    dict(sinks_per_lane=4, unroll=1, chunk=512, max_lanes=64),
+    dict(sinks_per_lane=4, unroll=4, chunk=256, max_lanes=3),
+    dict(sinks_per_lane=2, unroll=1, chunk=128, part_sources=1024),
+])
+def test_tile_cuts_of_cell_sizes(nf, cut_cells, tuning):
+    pos, K, eps, ref, pairs, mag = cut_cells
+    for mode in (0, 1, 2):
+        a, c = run(nf, pos, [(len(pos), 1.0, K)], [eps], [1.0 / len(pos)], SPLINE, mode, tuning=tuning)
+        assert c.interactions() == pairs
+        check(a, ref, mag, f"tile cuts {tuning} mode={mode}")
+        c.free()
+
+
 def _edge_case(case, rng):
     """(positions, [(n, L, K)], eps list, R)"""
     if case == "single":
@@ -241,6 +273,36 @@ def test_edge_cases(nf, case, kind):
         else:
             check(a, ref, mag, f"{case} kind={kind} mode={mode}")
         c.free()
+
+
+@pytest.mark.parametrize("K,off", [(5, (0.5, 0.5, 0.5)), (8, (0.125, 0.75, 0.3125)), (12, (0.0, 0.25, 0.875))])
+@pytest.mark.parametrize("kind", [SPLINE, PLUMMER])
+def test_lattice_has_zero_force(nf, K, off, kind):
+    """One particle per cell at a common dyadic offset (cell width 1/2): every sink sees a point-symmetric
+    source block whose separations are exact integers in cell widths, so its pair terms cancel in +/- pairs.
+    With FP64 sums the cancellation is exact (the FP32 terms span a few binades, so every partial sum is
+    exact in FP64): the force must be 0.  FP32 and compensated sums round each addition of at most 124
+    terms: |a_i| <= 124 * 2^-24 * S_i < 1e-5 S_i.  Softening 0.3 and 1 cell widths (the largest the library
+    accepts; Plummer softens every pair, the spline's neighbours all lie at r >= eps)."""
+    w = 0.5
+    box = K * w
+    g = np.stack(np.meshgrid(np.arange(K), np.arange(K), np.arange(K), indexing="ij"), -1).reshape(-1, 3)
+    pos = ((g + np.array(off)) * w).astype(np.float32)
+    assert np.array_equal(pos.astype(np.float64), (g + np.array(off)) * w)
+    gm = 1.0 / len(pos)
+    for eps_cells in (0.3, 1.0):
+        eps = eps_cells * w
+        ref, mag = oracle.forces(pos, box, K, 2, eps, kind, gm, return_mag=True)
+        assert np.abs(ref).max() <= 1e-13 * mag.max()
+        for mode in (0, 1, 2):
+            a, c = run(nf, pos, [(len(pos), box, K)], [eps], [gm], kind, mode)
+            ratio = float((np.linalg.norm(a, axis=1) / mag).max())
+            print(f"lattice K={K} kind={kind} eps={eps_cells} mode={mode}: max |a|/S = {ratio:.3e}", flush=True)
+            if mode == 2:
+                assert np.all(a == 0.0), (K, kind, eps_cells)
+            else:
+                assert ratio <= 1e-5, (K, kind, eps_cells, mode, ratio)
+            c.free()
 
 
 def test_forced_source_splitting_matches(nf):
@@ -319,6 +381,14 @@ def test_clustered_full_size_sampled(nf, clustered_full, mode):
     sinks = gen.sample_sinks(b.n, 3000, seed=99)
     ref, mag = oracle.forces(b.pos, b.box, b.K, 2, b.eps, SPLINE, b.gm, sinks=sinks, return_mag=True)
     check(a[sinks], ref, mag, f"clustered full mode={mode}")
+    # Newton's third law over all N sinks: the pair set is symmetric and each pair term antisymmetric, so
+    # sum_i a_i = 0 up to rounding.  The per-sink rounding is unbiased and of order 1e-6 |a_i| (FP32), so its
+    # sum is far below 1e-6 sum_i |a_i|; a missing or one-sided class of pairs (a column, a wrapped segment,
+    # a split part) leaves a net force of a sizeable fraction of the total.
+    net = np.linalg.norm(a.sum(axis=0))
+    scale = np.linalg.norm(a, axis=1).sum()
+    print(f"clustered full mode={mode}: |sum a| / sum |a| = {net / scale:.3e}", flush=True)
+    assert net <= 1e-6 * scale
     c.free()
 
 
