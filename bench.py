@@ -33,9 +33,12 @@ def log(msg):
 
 
 def kernel_source_digest() -> str:
-    """Digest of the force kernel's source file (a counter summary is valid only for these sources)."""
-    return hashlib.sha256(open(os.path.join(ROOT, "paper_2110_11398_amd", "csrc", "forces.hip"), "rb").read()
-                          ).hexdigest()[:16]
+    """Digest of the force kernel's sources: its file and the shared header that holds the tile geometry (a
+    counter summary is valid only for these sources)."""
+    h = hashlib.sha256()
+    for f in ("forces.hip", "nf_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2110_11398_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(workload: str, kind: str, mode: str, tuning: dict):
