@@ -218,8 +218,10 @@ def main():
                 med, p99, ns = frac_errors(acc.cpu().numpy(), parts)
                 line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, ns
                 if args.f64_out:
-                    # the same forces with FP64 output (no final FP32 rounding), an untimed extra call
+                    # the same forces with FP64 output (no final FP32 rounding), an untimed extra call with the
+                    # timed call's tuning (the same tiles, so the same summation order)
                     cells = nf.build_cells(pos, boxes, 2)
+                    cells.set_tuning(**{k: int(v) for k, v in line["config"]["tuning"].items()})
                     a64 = cells.forces_f64(eps, gm, KINDS[kname], MODES[mname])
                     med, p99, _ = frac_errors(a64.cpu().numpy(), parts)
                     line["median_frac_err_f64_out"], line["p99_frac_err_f64_out"] = med, p99
