@@ -333,29 +333,12 @@ __device__ inline void wave_lds_sync() {
 
 __device__ inline int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// One FP32 pair term: returns g with d = (dx, dy, dz) = source - sink.
-//   spline : g = min(r^-3, c0 + r2 (c1 r^-1 + c2)); the cubic force polynomial
-//            (divided by r) lies below r^-3 inside eps and above it outside, so
-//            the minimum selects the right branch without a compare (measured
-//            faster on gfx950 than a compare/select on r2 < eps2).
-//   Plummer: g = (r2 + eps2)^(-3/2).
-template <int KIND>
-__device__ __forceinline__ float pair_g(float dx, float dy, float dz, float c0, float c1, float c2, float e2,
-                                        float &r2) {
-    if constexpr (KIND == ABACUS_NF_PLUMMER) {
-        r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, e2)));
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float ri2 = ri * ri;
-        return ri2 * ri;
-    } else {
-        r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, kTiny)));
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float t = __builtin_fmaf(c1, ri, c2);
-        const float ri2 = ri * ri;
-        const float p = __builtin_fmaf(r2, t, c0);
-        const float ri3 = ri2 * ri;
-        return fminf(ri3, p);
-    }
+// Plummer pair term: g = (r2 + eps2)^(-3/2), with r2 = |d|^2 + eps2 returned.
+__device__ __forceinline__ float plummer_g(float dx, float dy, float dz, float e2, float &r2) {
+    r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, e2)));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    return ri2 * ri;
 }
 
 // Knuth's two-sum: s + e == a + b exactly.
@@ -377,27 +360,33 @@ __device__ __forceinline__ void accumulate(const float4 (&p)[U], const float (&x
     for (int u = 0; u < U; u++) {
         float dx[S], dy[S], dz[S], r2[S], gg[S];
         if constexpr (KIND == ABACUS_NF_SPLINE) {
-            // Newtonian regime test for the whole wave: when no lane has a pair closer than eps for this
-            // source, g = r^-3 exactly and the softening polynomial is skipped (one wave-uniform branch;
-            // close pairs are rare at the softening lengths of the method)
-            bool near = false;
+            // Spline: g = min(r^-3, c0 + r^2 (c1 r^-1 + c2)).  The cubic force polynomial (divided by r) lies
+            // below r^-3 inside eps and above it outside, so the minimum selects the right branch without a
+            // compare.  Newtonian regime test for the whole wave: when no lane has a pair closer than eps for
+            // this source, g = r^-3 exactly and the polynomial and the minimum are skipped (one wave-uniform
+            // branch; close pairs are rare at the softening lengths of the method).  r^2 > 0, so the bit
+            // patterns of r^2 order as unsigned integers like the values: one integer minimum per lane, one
+            // compare.
+            unsigned rmin = 0xffffffffu;
 #pragma unroll
             for (int s = 0; s < S; s++) {
                 dx[s] = p[u].x - xi[s];
                 dy[s] = p[u].y - yi[s];
                 dz[s] = p[u].z - zi[s];
                 r2[s] = __builtin_fmaf(dx[s], dx[s], __builtin_fmaf(dy[s], dy[s], __builtin_fmaf(dz[s], dz[s], kTiny)));
-                near = near || r2[s] < e2;
+                rmin = min(rmin, __float_as_uint(r2[s]));
             }
-            if (__builtin_amdgcn_ballot_w64(near)) {
+            float ri[S];
 #pragma unroll
-                for (int s = 0; s < S; s++) gg[s] = pair_g<KIND>(dx[s], dy[s], dz[s], c0, c1, c2, e2, r2[s]);
-            } else {
+            for (int s = 0; s < S; s++) {
+                ri[s] = __builtin_amdgcn_rsqf(r2[s]);
+                gg[s] = (ri[s] * ri[s]) * ri[s];
+            }
+            // some pair of the wave inside eps: the polynomial branch
+            if (__builtin_amdgcn_ballot_w64(rmin < __float_as_uint(e2))) {
 #pragma unroll
-                for (int s = 0; s < S; s++) {
-                    const float ri = __builtin_amdgcn_rsqf(r2[s]);
-                    gg[s] = (ri * ri) * ri;
-                }
+                for (int s = 0; s < S; s++)
+                    gg[s] = fminf(gg[s], __builtin_fmaf(r2[s], __builtin_fmaf(c1, ri[s], c2), c0));
             }
         } else {
 #pragma unroll
@@ -405,7 +394,7 @@ __device__ __forceinline__ void accumulate(const float4 (&p)[U], const float (&x
                 dx[s] = p[u].x - xi[s];
                 dy[s] = p[u].y - yi[s];
                 dz[s] = p[u].z - zi[s];
-                gg[s] = pair_g<KIND>(dx[s], dy[s], dz[s], c0, c1, c2, e2, r2[s]);
+                gg[s] = plummer_g(dx[s], dy[s], dz[s], e2, r2[s]);
             }
         }
 #pragma unroll
