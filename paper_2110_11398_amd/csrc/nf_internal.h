@@ -64,9 +64,10 @@ struct WorkState {
 // group per lane); a tile of G groups gives each group L = 64 / G lanes (at most
 // max_lanes), which split the sources between them.  Whole tiles of 64 groups
 // (L = 1) come first.  A rest of r < 64 groups is one tile when that tile keeps
-// at least 7/8 of the wave's lanes busy, when L is at its cap, or when r is a
-// power of two; otherwise a tile of the largest power of two k < r groups
-// (L = 64 / k, every lane busy) is cut off and the rest follows the same rule.
+// at least 7/8 of the wave's lanes busy, when r is a power of two, or when the
+// cut below would need more than max_lanes lanes per group; otherwise a tile of
+// the largest power of two k < r groups (L = 64 / k, every lane busy) is cut
+// off and the rest follows the same rule.
 // So every tile but a cell's last fills its wave (e.g. 43 groups: 32 with L = 2,
 // 8 with L = 8, 3 with L = 21), and tile 0 has the fewest lanes per group.
 struct TileGeom {
