@@ -174,18 +174,49 @@ __global__ __launch_bounds__(64) void k_ts_units(TsArgs a) {
         const int after = s1 < a.n ? a.keys[s1] : -1;
         double carry[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
         int carry_key = -1;
-        // the next batch's keys and permutation entries are loaded while the current one is reduced
+        // two-deep pipeline: while a batch is reduced, the velocities, accelerations and reference velocities
+        // of the next batch are in flight (gathered through the permutation), and the keys and permutation
+        // entries of the batch after it
         int key_n = s0 + lane < s1 ? a.keys[s0 + lane] : -2;
         int perm_n = s0 + lane < s1 ? a.perm[s0 + lane] : 0;
+        float v_n[3] = {0.f, 0.f, 0.f}, g_n[3] = {0.f, 0.f, 0.f}, r_n[3] = {0.f, 0.f, 0.f};
+        if (s0 + lane < s1) {
+            const float *vr = a.ref + 3 * (int64_t)key_n;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                v_n[d] = a.vel[3 * (int64_t)perm_n + d];
+                g_n[d] = a.acc[3 * (int64_t)perm_n + d];
+                r_n[d] = vr[d];
+            }
+        }
+        int key_nn = s0 + 64 + lane < s1 ? a.keys[s0 + 64 + lane] : -2;
+        int perm_nn = s0 + 64 + lane < s1 ? a.perm[s0 + 64 + lane] : 0;
         for (int64_t b0 = s0; b0 < s1; b0 += 64) {
             const int nb = (int)(s1 - b0 < 64 ? s1 - b0 : 64);
             const bool live = lane < nb;
             const int key = key_n;
-            const int64_t i = perm_n;
-            const int64_t b1 = b0 + 64;
+            float v[3], g[3], r[3];
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                v[d] = v_n[d];
+                g[d] = g_n[d];
+                r[d] = r_n[d];
+            }
+            const int64_t b1 = b0 + 64, b2 = b0 + 128;
             const bool live_n = b1 + lane < s1;
-            key_n = live_n ? a.keys[b1 + lane] : -2;
-            perm_n = live_n ? a.perm[b1 + lane] : 0;
+            key_n = key_nn;
+            perm_n = perm_nn;
+            if (live_n) {
+                const float *vr = a.ref + 3 * (int64_t)key_n;
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    v_n[d] = a.vel[3 * (int64_t)perm_n + d];
+                    g_n[d] = a.acc[3 * (int64_t)perm_n + d];
+                    r_n[d] = vr[d];
+                }
+            }
+            key_nn = b2 + lane < s1 ? a.keys[b2 + lane] : -2;
+            perm_nn = b2 + lane < s1 ? a.perm[b2 + lane] : 0;
             const int first_next = __builtin_amdgcn_readfirstlane(key_n);   // cell of slot b1 when b1 < s1
             const int prevk = __shfl_up(key, 1);
             int nxt = __shfl_down(key, 1);
@@ -194,11 +225,10 @@ __global__ __launch_bounds__(64) void k_ts_units(TsArgs a) {
             const uint64_t endmask = __ballot(end);
             double x[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if (live) {
-                const float *vr = a.ref + 3 * (int64_t)key;
-                const double dx = (double)a.vel[3 * i + 0] - (double)vr[0];
-                const double dy = (double)a.vel[3 * i + 1] - (double)vr[1];
-                const double dz = (double)a.vel[3 * i + 2] - (double)vr[2];
-                const double ax = a.acc[3 * i + 0], ay = a.acc[3 * i + 1], az = a.acc[3 * i + 2];
+                const double dx = (double)v[0] - (double)r[0];
+                const double dy = (double)v[1] - (double)r[1];
+                const double dz = (double)v[2] - (double)r[2];
+                const double ax = g[0], ay = g[1], az = g[2];
                 x[0] = dx;
                 x[1] = dy;
                 x[2] = dz;
