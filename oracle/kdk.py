@@ -72,6 +72,17 @@ def cell_timestep(pos, vel, acc, box: float, K: int, eta: float = 0.25) -> float
     return float(eta * best)
 
 
+def cell_max_accel(pos, acc, box: float, K: int) -> np.ndarray:
+    """Largest |a| over the particles of each cell (FP64 from the FP32 values; 0 for an empty cell), [K^3].
+
+    The per-cell input of the step-size criterion (Sec. 2.5, time stepping)."""
+    cells = _orc.bin_cells(pos, box, K).astype(np.int64)
+    a = np.asarray(acc, dtype=np.float32).astype(np.float64)
+    out = np.zeros(K ** 3)
+    np.maximum.at(out, cells, np.sqrt((a ** 2).sum(axis=1)))
+    return out
+
+
 def kdk_step(pos, vel, dt: float, box: float, force, acc=None):
     """One leapfrog step of size dt with accelerations force(pos) (FP64 [n, 3]); returns (pos, vel, acc)
     after the step: FP32 positions and velocities, and the accelerations at the new positions (the next

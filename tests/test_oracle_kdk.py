@@ -129,9 +129,21 @@ def pin_timestep_is_the_minimum_over_cells(m):
     return abs(base - 0.25 * r0) <= 1e-14 * base and abs(got2 - want2) <= 1e-14 * want2 and got2 > base
 
 
+def pin_cell_max_accel_closed_form(m):
+    """K=2: cell 0 holds accelerations of norm 5 (3-4-0) and 13 (5-12-0), cell 7 one of norm 1 and one of
+    norm 3 (2-2-1), cell 3 one of norm 7 (2-3-6); the other five cells are empty."""
+    pos = np.array([[0.1, 0.1, 0.1], [0.3, 0.2, 0.4], [0.7, 0.8, 0.9], [0.6, 0.6, 0.6], [0.2, 0.7, 0.8]],
+                   np.float32)
+    acc = np.array([[3, 4, 0], [5, 12, 0], [0, 0, -1], [2, -2, 1], [2, 3, 6]], np.float32)
+    got = m.cell_max_accel(pos, acc, 1.0, 2)
+    want = np.zeros(8)
+    want[0], want[7], want[3] = 13.0, 3.0, 7.0
+    return np.array_equal(got, want)
+
+
 PINS = [pin_kick_closed_form, pin_drift_wraps, pin_drift_round_up_to_box_is_zero, pin_free_streaming,
         pin_second_order, pin_time_reversible, pin_momentum_conserved, pin_timestep_closed_form,
-        pin_timestep_is_the_minimum_over_cells]
+        pin_timestep_is_the_minimum_over_cells, pin_cell_max_accel_closed_form]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda p: p.__name__)
@@ -156,6 +168,12 @@ KDK_MUTANTS = {
                           "amax = np.sqrt((a[idx] ** 2).sum(axis=1)).mean()"),
     "lone_particles_counted": ("if idx.size < 2:", "if idx.size < 1:"),
     "eta_dropped": ("return float(eta * best)", "return float(best)"),
+    "cell_max_is_sum": ("np.maximum.at(out, cells, np.sqrt((a ** 2).sum(axis=1)))",
+                        "np.add.at(out, cells, np.sqrt((a ** 2).sum(axis=1)))"),
+    "cell_max_of_squares": ("np.maximum.at(out, cells, np.sqrt((a ** 2).sum(axis=1)))",
+                            "np.maximum.at(out, cells, (a ** 2).sum(axis=1))"),
+    "cell_max_l1": ("np.maximum.at(out, cells, np.sqrt((a ** 2).sum(axis=1)))",
+                    "np.maximum.at(out, cells, np.abs(a).sum(axis=1))"),
 }
 
 
