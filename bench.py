@@ -4,8 +4,13 @@ One step = abacus_nf_build_cells + abacus_nf_forces over one batch of the
 workload (all of binning, sort, cell offsets, layout, work list, pairwise
 kernel and finalize), inputs already resident in HBM.  Prints one JSON line.
 
-Default workload: the clustered plain-FP32 configuration (N=256^3, K=64,
-50% in 4096 Plummer halos, spline softening eps = spacing/40).
+Default: the late-time workload (N=2^27, K=256, half of the particles in 1% of
+the cells), spline softening, compensated FP32 sums (the largest single-GPU
+configuration of the metric), with its median / p99 fractional error on 10^5
+sampled sinks against the FP64 oracle.  The same line carries, under
+"variants", the plain FP32 sums and the Plummer kernel on the same workload and
+the 64 batched boxes as one HIP-graph replay in both summation modes (a few
+steps each, errors on smaller samples).
 """
 from __future__ import annotations
 
@@ -24,6 +29,8 @@ sys.path.insert(0, ROOT)
 METRIC = "near-field interactions/s + particle updates/s, 1 GPU, median frac err ≤1e-5"
 FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak (256 CUs x 2.4 GHz x 64 lanes x 2 FMA x 2 packed)
 FLOPS_PER_PAIR = {0: 26, 1: 20}   # the paper's convention: op = 1, rsqrt = 2 (spline 26; Plummer 20)
+FLOP_CONVENTION = ("Sec. 4.3 convention: every operation 1, rsqrt 2, per evaluated pair: 26 (spline: polynomial, "
+                   "compare and select counted for every pair), 20 (Plummer)")
 MODES = {"fp32": 0, "comp32": 1, "fp64": 2}
 KINDS = {"spline": 0, "plummer": 1}
 
@@ -41,10 +48,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, kind: str, mode: str, tuning: dict):
-    """HBM bytes per force-kernel launch from a committed counter summary, if it was taken on these
-    kernel sources with this kernel variant (otherwise None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_forces_{workload}_{kind}_{mode}.json")
+def counter_summary(what: str, workload: str, kind: str, mode: str, tuning: dict):
+    """A committed counter summary of the force kernel (profiles/<what>_forces_<workload>_<kind>_<mode>.json),
+    if it was taken on these kernel sources with this kernel variant (otherwise None)."""
+    path = os.path.join(ROOT, "profiles", f"{what}_forces_{workload}_{kind}_{mode}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -56,7 +63,20 @@ def traffic_from_profile(workload: str, kind: str, mode: str, tuning: dict):
     for k in ("sinks_per_lane", "unroll", "chunk", "occupancy", "max_lanes"):
         if d.get("tuning", {}).get(k) != tuning.get(k):
             return None
-    return d.get("bytes_per_launch")
+    return d
+
+
+def traffic_from_profile(workload: str, kind: str, mode: str, tuning: dict):
+    """HBM bytes per force-kernel launch from a committed FETCH_SIZE / WRITE_SIZE summary (or None)."""
+    d = counter_summary("traffic", workload, kind, mode, tuning)
+    return d.get("bytes_per_launch") if d else None
+
+
+def executed_flops_from_profile(workload: str, kind: str, mode: str, tuning: dict):
+    """FP32 operations the hardware executed per pair (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS) from a committed
+    counter summary (or None)."""
+    d = counter_summary("valu", workload, kind, mode, tuning)
+    return d.get("executed_flops_per_pair") if d else None
 
 
 def oracle_sample(boxes, kind, target_s, threads, m_fixed=0):
@@ -104,19 +124,44 @@ def oracle_sample(boxes, kind, target_s, threads, m_fixed=0):
     d1 = time.perf_counter() - t0
     base["single_core"] = {"value": p1 / d1, "unit": "interactions/s", "cores": 1,
                            "sample": f"{m1} sinks of box 0 (seed 99); {p1} FP64 pairs in {d1:.2f} s"}
-    base["cpu_model"] = cpu_model()
+    base.update(host_description())
     return base, parts
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (from /proc/cpuinfo), or an empty string."""
+    """The host CPU as /proc/cpuinfo names it: model name, vendor, family / model / stepping."""
+    fields = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "vendor_id", "cpu family", "model", "stepping") and k not in fields:
+                    fields[k] = v
+            if not line.strip() and fields:
+                break
     except OSError:
         pass
-    return ""
+    if not fields:
+        return ""
+    return (f"{fields.get('model name', '')} ({fields.get('vendor_id', '')}, family {fields.get('cpu family', '?')} "
+            f"model {fields.get('model', '?')} stepping {fields.get('stepping', '?')})")
+
+
+def oracle_threads() -> int:
+    """Threads for the oracle: the host CPU share this process is given (OMP_NUM_THREADS when set, as on a
+    GPU machine where each GPU owns a share of the host), else every CPU it may run on."""
+    visible = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        share = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        share = 0
+    return max(1, min(visible, share) if share > 0 else visible)
+
+
+def host_description() -> dict:
+    return {"cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "cpus_available": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def frac_errors(acc_all, parts):
@@ -135,13 +180,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="clustered", choices=["tiny", "clustered", "precision", "batched", "late"])
+    ap.add_argument("--workload", default="late", choices=["tiny", "clustered", "precision", "batched", "late"])
     ap.add_argument("--kind", default="spline", help="spline, plummer, or a comma list")
-    ap.add_argument("--mode", default="fp32", help="fp32, comp32, fp64, or a comma list")
-    ap.add_argument("--err-sinks", type=int, default=0,
-                    help="fixed size of the oracle sample (default: sized to about --cpu-seconds)")
+    ap.add_argument("--mode", default="comp32", help="fp32, comp32, fp64, or a comma list")
+    ap.add_argument("--err-sinks", type=int, default=100000,
+                    help="size of the oracle sample for the errors and the CPU baseline (0: sized to about "
+                         "--cpu-seconds)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="auto", choices=["auto", "on", "off"],
+                    help="also run, and nest in the same line, plain FP32 sums and the Plummer kernel on the same "
+                         "workload and the batched boxes as one HIP-graph replay (auto: with the default workload, "
+                         "kind and mode)")
+    ap.add_argument("--variant-steps", type=int, default=3)
+    ap.add_argument("--variant-err-sinks", type=int, default=30000)
     ap.add_argument("--f64-out", action="store_true",
                     help="also report the errors of the FP64 output (abacus_nf_forces_f64) on the oracle sample")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2110_11398_amd", "tuning_cache.json"),
@@ -180,9 +232,6 @@ def main():
     w = gen.workload(args.workload)
     log(f"generated {args.workload}: N={w.n_total} boxes={len(w.boxes)} in {time.perf_counter() - t0:.1f} s")
     pos = torch.from_numpy(w.concat_positions()).cuda()
-    boxes = [(b.n, b.box, b.K) for b in w.boxes]
-    eps = [b.eps for b in w.boxes]
-    gm = [b.gm for b in w.boxes]
     acc = torch.empty((w.n_total, 3), dtype=torch.float32, device="cuda")
     if args.copy_calibration_mb > 0:
         nbytes = args.copy_calibration_mb << 20
@@ -193,6 +242,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    eps = [b.eps for b in w.boxes]
+    gm = [b.gm for b in w.boxes]
     if args.stage == "multipoles":
         print(json.dumps(run_multipoles(args, nf, torch, w, pos, boxes)), flush=True)
         return
@@ -202,21 +254,32 @@ def main():
     if args.stage == "kdk":
         print(json.dumps(run_kdk(args, nf, torch, w, pos, boxes, eps, gm, acc)), flush=True)
         return
-    threads = min(16, os.cpu_count() or 1)
+    variants = args.variants == "on" or (args.variants == "auto" and args.workload == "late" and
+                                         args.kind == "spline" and args.mode == "comp32" and not args.density
+                                         and not args.graph and not args.tuning)
+    threads = oracle_threads()
     samples = {}
+
+    def errors_of(line, kind, m_fixed, with_baseline):
+        """Median / p99 fractional error of acc on the oracle sample of this kind (timed once per kind)."""
+        if kind not in samples:
+            samples[kind] = oracle_sample(w.boxes, kind, args.cpu_seconds, threads, m_fixed)
+        base, parts = samples[kind]
+        if with_baseline:
+            line["cpu_baseline"] = dict(base)
+            # full step on the oracle, extrapolated from its measured rate (not run)
+            line["cpu_baseline"]["extrapolated_full_step_s"] = line["config"]["interactions_per_step"] / base["value"]
+        med, p99, ns = frac_errors(acc.cpu().numpy(), parts)
+        line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, ns
+        return parts
+
+    lines = []
     for kname in args.kind.split(","):
         for mname in args.mode.split(","):
-            line = run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, KINDS[kname], MODES[mname], kname, mname)
+            line = run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, KINDS[kname], MODES[mname], kname, mname,
+                           args.steps, args.warmup, args.graph)
             if not args.no_cpu_baseline:
-                kind = KINDS[kname]
-                if kind not in samples:
-                    samples[kind] = oracle_sample(w.boxes, kind, args.cpu_seconds, threads, args.err_sinks)
-                base, parts = samples[kind]
-                line["cpu_baseline"] = dict(base)
-                # full step on the oracle, extrapolated from its measured rate (not run)
-                line["cpu_baseline"]["extrapolated_full_step_s"] = line["config"]["interactions_per_step"] / base["value"]
-                med, p99, ns = frac_errors(acc.cpu().numpy(), parts)
-                line["median_frac_err"], line["p99_frac_err"], line["err_sample_sinks"] = med, p99, ns
+                parts = errors_of(line, KINDS[kname], args.err_sinks, True)
                 if args.f64_out:
                     # the same forces with FP64 output (no final FP32 rounding), an untimed extra call with the
                     # timed call's tuning (the same tiles, so the same summation order)
@@ -226,10 +289,54 @@ def main():
                     med, p99, _ = frac_errors(a64.cpu().numpy(), parts)
                     line["median_frac_err_f64_out"], line["p99_frac_err_f64_out"] = med, p99
                     cells.free()
-            print(json.dumps(line), flush=True)
+            lines.append(line)
+    if variants:
+        head = lines[0]
+        out = {}
+        # the same workload: plain FP32 sums (errors on the spline sample), and the Plummer kernel
+        for kname, mname in (("spline", "fp32"), ("plummer", "comp32")):
+            v = run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, KINDS[kname], MODES[mname], kname, mname,
+                        args.variant_steps, 1, False)
+            if not args.no_cpu_baseline:
+                errors_of(v, KINDS[kname], args.variant_err_sinks, False)
+            out[f"{args.workload}/{kname}/{mname}"] = compact(v)
+        del pos
+        torch.cuda.empty_cache()
+        # the batched boxes, build + forces captured once in a HIP graph and replayed
+        wb = gen.workload("batched")
+        log(f"generated batched: N={wb.n_total} boxes={len(wb.boxes)}")
+        pb = torch.from_numpy(wb.concat_positions()).cuda()
+        ab = torch.empty((wb.n_total, 3), dtype=torch.float32, device="cuda")
+        bb = [(b.n, b.box, b.K) for b in wb.boxes]
+        eb, gb = [b.eps for b in wb.boxes], [b.gm for b in wb.boxes]
+        _, bparts = oracle_sample(wb.boxes, KINDS["spline"], args.cpu_seconds, threads,
+                                  args.variant_err_sinks) if not args.no_cpu_baseline else (None, None)
+        for mname in ("comp32", "fp32"):
+            v = run_one(args, nf, torch, wb, pb, bb, eb, gb, ab, KINDS["spline"], MODES[mname], "spline", mname,
+                        args.variant_steps, 1, True)
+            if bparts is not None:
+                med, p99, ns = frac_errors(ab.cpu().numpy(), bparts)
+                v["median_frac_err"], v["p99_frac_err"], v["err_sample_sinks"] = med, p99, ns
+            out[f"batched-graph/spline/{mname}"] = compact(v)
+        head["variants"] = out
+    for line in lines:
+        print(json.dumps(line), flush=True)
 
 
-def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mname):
+def compact(line):
+    """The fields of a variant kept in the headline's JSON line."""
+    keep = ("value", "unit", "ms_per_step", "steps", "particle_updates_per_s", "median_frac_err", "p99_frac_err",
+            "err_sample_sinks")
+    out = {k: line[k] for k in keep if k in line}
+    out["config"] = {k: line["config"][k] for k in ("workload", "n", "boxes", "kind", "mode", "interactions_per_step",
+                                                    "tuning", "hip_graph")}
+    out["stages_ms"] = line["stages_ms"]
+    out["roofline"] = {k: line["roofline"][k] for k in ("achieved", "frac", "frac_executed", "kernel_ms")
+                       if k in line["roofline"]}
+    return out
+
+
+def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mname, steps, warmup, use_graph):
     cells = nf.build_cells(pos, boxes, 2)
     rho = torch.empty(w.n_total, dtype=torch.float32, device="cuda") if args.density else None
     bk = [0.4 * b.box / b.n ** (1.0 / 3.0) if b.n else b.box / b.K for b in w.boxes]
@@ -253,13 +360,13 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
     interactions = cells.interactions()
     log(f"interactions per step: {interactions:.6e}")
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         nf.build_cells(pos, boxes, 2, cells=cells)
         step_forces()
     nf.sync()
 
     graph = None
-    if args.graph:
+    if use_graph:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             nf.build_cells(pos, boxes, 2, cells=cells)
@@ -274,7 +381,7 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         if graph is not None:
             graph.replay()
         else:
@@ -284,19 +391,20 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
     e1.record()
     torch.cuda.synchronize()
     nf.sync()
-    ms_step = e0.elapsed_time(e1) / args.steps
-    stage_ms /= args.steps
+    ms_step = e0.elapsed_time(e1) / steps
+    stage_ms /= steps
     if graph is not None:
         cells.set_timing(True)
         stage_ms = np.zeros(4)
-        for _ in range(args.steps):
+        for _ in range(steps):
             nf.build_cells(pos, boxes, 2, cells=cells)
             step_forces()
             stage_ms += np.array(cells.last_times())
-        stage_ms /= args.steps
+        stage_ms /= steps
         nf.sync()
+        del graph
     cells.set_timing(False)
-    log(f"[{kname}/{mname}] ms/step {ms_step:.3f}; stages ms build={stage_ms[0]:.3f} "
+    log(f"[{w.name} {kname}/{mname}] ms/step {ms_step:.3f}; stages ms build={stage_ms[0]:.3f} "
         f"worklist={stage_ms[1]:.3f} kernel={stage_ms[2]:.3f} finalize={stage_ms[3]:.3f}")
 
     step_s = ms_step / 1e3
@@ -305,15 +413,23 @@ def run_one(args, nf, torch, w, pos, boxes, eps, gm, acc, kind, mode, kname, mna
     achieved = FLOPS_PER_PAIR[kind] * interactions / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": traffic_from_profile(args.workload, kname, mname, tuning),
+                "traffic": traffic_from_profile(w.name, kname, mname, tuning),
                 "kernel": "k_forces", "kernel_ms": stage_ms[2],
-                "flops_per_launch": FLOPS_PER_PAIR[kind] * interactions}
+                "flops_per_launch": FLOPS_PER_PAIR[kind] * interactions,
+                "flop_convention": FLOP_CONVENTION,
+                "pairs_per_s_kernel": interactions / kern_s}
+    executed = executed_flops_from_profile(w.name, kname, mname, tuning)
+    if executed is not None:
+        # the same launch counted by the hardware's FLOP counters (the Newtonian fast path skips the softening
+        # polynomial, so fewer operations execute than the convention credits)
+        roofline["executed_flops_per_pair"] = executed
+        roofline["frac_executed"] = executed * interactions / kern_s / 1e12 / FP32_PEAK_TFLOPS
     out = {"metric": METRIC, "value": interactions / step_s, "unit": "interactions/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "steps": steps, "warmup": warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"{args.workload}: {w.description}", "n": w.n_total, "boxes": len(w.boxes),
+           "config": {"workload": f"{w.name}: {w.description}", "n": w.n_total, "boxes": len(w.boxes),
                       "K": [b.K for b in w.boxes][:4], "kind": kname, "mode": mname,
-                      "interactions_per_step": interactions, "tuning": tuning, "hip_graph": bool(args.graph),
+                      "interactions_per_step": interactions, "tuning": tuning, "hip_graph": bool(use_graph),
                       "density": bool(args.density)},
            "particle_updates_per_s": w.n_total / step_s,
            "particle_updates_per_s_forces_only": w.n_total / ((stage_ms[1] + stage_ms[2] + stage_ms[3]) / 1e3),
@@ -415,6 +531,10 @@ def run_kdk(args, nf, torch, w, pos, boxes, eps, gm, acc):
             cells.reorder([pos, vel, acc])
 
     ms = _time_calls(args, torch, nf, step)
+    # the step-size criterion on the state after the steps: from the gathered accelerations, and from the
+    # per-cell maxima the last force pass recorded (each call blocks for its n_boxes results)
+    ts_ms = _time_calls(args, torch, nf, lambda: cells.timestep(vel, acc, 0.25))
+    ts_fused_ms = _time_calls(args, torch, nf, lambda: cells.timestep(vel, None, 0.25))
     probe = torch.empty_like(vel)
     kick_ms = _time_calls(args, torch, nf, lambda: cells.kick(dt, acc, probe))
     drift_ms = _time_calls(args, torch, nf, lambda: cells.drift([0.0] * len(boxes), probe, pos))
@@ -428,6 +548,7 @@ def run_kdk(args, nf, torch, w, pos, boxes, eps, gm, acc):
                        "merge_each_step": bool(args.merge),
                        "interactions_per_step_at_start": pairs, "tuning": cells.get_tuning().as_dict()},
             "interactions_per_s_at_start": pairs / (ms / 1e3),
+            "timestep_call_ms": {"gathered_acc": ts_ms, "force_pass_maxima": ts_fused_ms},
             "kick": {"ms": kick_ms, "GB/s": stream_bytes / (kick_ms / 1e3) / 1e9,
                      "frac_hbm": stream_bytes / (kick_ms / 1e3) / 1e9 / 8000.0},
             "drift": {"ms": drift_ms, "GB/s": stream_bytes / (drift_ms / 1e3) / 1e9,

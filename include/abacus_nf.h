@@ -230,12 +230,18 @@ int abacus_nf_drift(abacus_nf_cells cells, const double *dt, const float *vel, f
  * Cells with fewer than two particles or no nonzero acceleration do not
  * constrain the step; a box without a constraining cell gets +inf.  The cells
  * must be built from the positions the velocities and accelerations belong to.
+ *   vel     device float32 [n_total][3], input order.
+ *   acc     device float32 [n_total][3], input order; or NULL to take max |a_j|
+ *           of each cell from the last forces call on this handle since its
+ *           last build (the force pass records the largest |a|^2 it writes in
+ *           each cell; ESTATE if there was no such call).  Accelerations
+ *           changed after that call (a far-field co-add) are not seen then.
  *   eta     > 0 (AbacusSummit uses 0.25).
  *   dt_out  host double [n_boxes].
  * Sums are FP64 (velocities taken relative to the first particle of each
- * cell); the minimum is exact.  Blocks on the stream (copies n_boxes doubles
- * to the host).  The first call (or one with a larger batch) allocates its
- * partials buffer.
+ * cell); |a|^2 is the FP64 sum of the squared FP32 components; the minimum is
+ * exact.  Blocks on the stream (copies n_boxes doubles to the host).  The
+ * first call (or one with a larger batch) allocates its partials buffer.
  */
 int abacus_nf_timestep(abacus_nf_cells cells, const float *vel, const float *acc, double eta, double *dt_out,
                        void *hip_stream);
@@ -295,7 +301,11 @@ typedef enum {
     ABACUS_NF_ARRAY_CELL_START = 1, /* int32 [n_cells + 1]: first slot of each cell (all boxes)   */
     ABACUS_NF_ARRAY_SPOS = 2,       /* float32 [n_total][4]: cell-relative x, y, z in cell widths,
                                        and the z cell index, per sorted slot                      */
-    ABACUS_NF_ARRAY_CELL_KEY = 3    /* int32 [n_total]: global cell index of each sorted slot     */
+    ABACUS_NF_ARRAY_CELL_KEY = 3,   /* int32 [n_total]: global cell index of each sorted slot     */
+    ABACUS_NF_ARRAY_CELL_AMAX2 = 4  /* float64 [n_cells]: largest |a|^2 over each cell's particles
+                                       as written by the last forces call since the last build
+                                       (FP64 sum of the squared written components; 0 for an
+                                       empty cell); ESTATE before such a call                    */
 } abacus_nf_array;
 
 /* Number of particles and of cells (all boxes) of a built handle. */

@@ -8,9 +8,9 @@ GPU; every call that computes needs the built library and a GPU and raises
 otherwise.
 """
 from .abacus_nf import (SPLINE, PLUMMER, SUM_FP32, SUM_COMP32, SUM_FP64, ARRAY_PERM, ARRAY_CELL_START, ARRAY_SPOS,
-                        ARRAY_CELL_KEY, NearFieldError, Cells, Tuning, build_cells, forces, sync, near_field,
+                        ARRAY_CELL_KEY, ARRAY_CELL_AMAX2, NearFieldError, Cells, Tuning, build_cells, forces, sync, near_field,
                         library, library_path, strerror, version)
 
 __all__ = ["SPLINE", "PLUMMER", "SUM_FP32", "SUM_COMP32", "SUM_FP64", "ARRAY_PERM", "ARRAY_CELL_START", "ARRAY_SPOS",
-           "ARRAY_CELL_KEY", "NearFieldError", "Cells", "Tuning", "build_cells", "forces", "sync", "near_field",
+           "ARRAY_CELL_KEY", "ARRAY_CELL_AMAX2", "NearFieldError", "Cells", "Tuning", "build_cells", "forces", "sync", "near_field",
            "library", "library_path", "strerror", "version"]

@@ -17,7 +17,7 @@ _LIB_PATH = os.environ.get("ABACUS_NF_LIBRARY") or os.path.join(HERE, "libabacus
 
 SPLINE, PLUMMER = 0, 1
 SUM_FP32, SUM_COMP32, SUM_FP64 = 0, 1, 2
-ARRAY_PERM, ARRAY_CELL_START, ARRAY_SPOS, ARRAY_CELL_KEY = 0, 1, 2, 3
+ARRAY_PERM, ARRAY_CELL_START, ARRAY_SPOS, ARRAY_CELL_KEY, ARRAY_CELL_AMAX2 = 0, 1, 2, 3, 4
 
 OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 
@@ -261,10 +261,12 @@ class Cells:
         _check(rc, "abacus_nf_drift")
         return pos
 
-    def timestep(self, vel, acc, eta: float = 0.25, stream=None) -> List[float]:
-        """abacus_nf_timestep: eta * min over cells of sigma_v / max|a|, per box (blocks on the stream)."""
+    def timestep(self, vel, acc=None, eta: float = 0.25, stream=None) -> List[float]:
+        """abacus_nf_timestep: eta * min over cells of sigma_v / max|a|, per box (blocks on the stream).
+        With acc=None the per-cell maxima of |a| come from the last forces call on this handle."""
         out = (ctypes.c_double * len(self.boxes))()
-        rc = library().abacus_nf_timestep(self._h, self._vec3(vel, "vel"), self._vec3(acc, "acc"), float(eta), out,
+        a = self._vec3(acc, "acc") if acc is not None else ctypes.c_void_p(None)
+        rc = library().abacus_nf_timestep(self._h, self._vec3(vel, "vel"), a, float(eta), out,
                                           ctypes.c_void_p(_stream_handle(stream)))
         _check(rc, "abacus_nf_timestep")
         return list(out)
@@ -311,6 +313,8 @@ class Cells:
         n, nc = self.size()
         if which == ARRAY_SPOS:
             t = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        elif which == ARRAY_CELL_AMAX2:
+            t = torch.empty(nc, dtype=torch.float64, device="cuda")
         elif which == ARRAY_CELL_START:
             t = torch.empty(nc + 1, dtype=torch.int32, device="cuda")
         else:

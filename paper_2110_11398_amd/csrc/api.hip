@@ -43,8 +43,6 @@ struct abacus_nf_cells_s {
     unsigned long long *ts_min = nullptr;   // [n_boxes]
     size_t ts_cap = 0;
     double *ts_partials = nullptr;
-    int64_t ts_ref_cap = 0;
-    float *ts_ref = nullptr;                // [n_cells][3] reference velocities
     // merge scratch (n_total x 12 bytes)
     size_t merge_cap = 0;
     void *merge_tmp = nullptr;
@@ -58,6 +56,10 @@ struct abacus_nf_cells_s {
     int64_t *cell_pdem = nullptr, *cell_pbase = nullptr;
     double *partials = nullptr;
     void *wscan_temp = nullptr;
+    // largest |a|^2 per cell (bits of a non-negative double) written by the last forces call; valid until
+    // the next build
+    unsigned long long *cell_amax = nullptr;
+    bool amax_valid = false;
 
     // persistent-kernel grid of the last (kind, mode, tuning): queried once, outside any capture
     int grid = 0;
@@ -137,10 +139,8 @@ void free_step_buffers(abacus_nf_cells_s *h) {
     dfree(h->d_dt);
     dfree(h->ts_min);
     dfree(h->ts_partials);
-    dfree(h->ts_ref);
     h->scap_boxes = -1;
     h->ts_cap = 0;
-    h->ts_ref_cap = 0;
     if (h->merge_tmp) hipFree(h->merge_tmp);
     h->merge_tmp = nullptr;
     h->merge_cap = 0;
@@ -148,7 +148,8 @@ void free_step_buffers(abacus_nf_cells_s *h) {
 
 void free_work_buffers(abacus_nf_cells_s *h) {
     dfree(h->d_fbox); dfree(h->ws); dfree(h->items); dfree(h->cell_nsrc); dfree(h->cell_parts);
-    dfree(h->cell_pdem); dfree(h->cell_pbase); dfree(h->partials);
+    dfree(h->cell_pdem); dfree(h->cell_pbase); dfree(h->partials); dfree(h->cell_amax);
+    h->amax_valid = false;
     if (h->wscan_temp) hipFree(h->wscan_temp);
     h->wscan_temp = nullptr;
     h->wcap_cells = h->wcap_items = h->wcap_partials = h->wcap_boxes = -1;
@@ -307,6 +308,7 @@ int abacus_nf_build_cells(const float *pos, int64_t n_total, const abacus_nf_box
     h->boxes.assign(boxes, boxes + n_boxes);
     h->cell_base = base;
     h->built = false;
+    h->amax_valid = false;
     *cells = h;
 
     // ---- enqueue
@@ -360,7 +362,7 @@ static int ensure_work_buffers(abacus_nf_cells_s *h) {
     free_work_buffers(h);
     bool ok = dalloc(h->d_fbox, h->n_boxes) && dalloc(h->ws, 1) && dalloc(h->items, want_items) &&
               dalloc(h->cell_nsrc, nc) && dalloc(h->cell_parts, nc) && dalloc(h->cell_pdem, nc) &&
-              dalloc(h->cell_pbase, nc) && dalloc(h->partials, 4 * want_partials) &&
+              dalloc(h->cell_pbase, nc) && dalloc(h->partials, 4 * want_partials) && dalloc(h->cell_amax, nc) &&
               dalloc_bytes(h->wscan_temp, scan_temp_bytes(nc));
     if (!ok) {
         free_work_buffers(h);
@@ -395,6 +397,7 @@ static ForcesArgs make_args(abacus_nf_cells_s *h, abacus_nf_kind kind, abacus_nf
     a.cell_pbase = h->cell_pbase;
     a.partials = h->partials;
     a.partial_capacity = h->wcap_partials;
+    a.amax = h->cell_amax;
     a.acc = acc;
     a.rho = nullptr;
     a.err = err;
@@ -424,7 +427,11 @@ static int forces_impl(abacus_nf_cells h, const double *eps, abacus_nf_kind kind
     if (!err) return ABACUS_NF_ENOMEM;
     if ((rc = ensure_work_buffers(h)) != ABACUS_NF_OK) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    if (h->n_total == 0) return ABACUS_NF_OK;
+    if (h->n_total == 0) {   // every cell is empty: its largest |a|^2 is 0
+        if (hipError_t e = launch_fill_u64(h->cell_amax, h->n_cells, 0ull, st); e != hipSuccess) return hip_fail(e);
+        h->amax_valid = true;
+        return ABACUS_NF_OK;
+    }
     ForcesArgs a = make_args(h, kind, mode, acc, err);
     a.acc64 = acc64;
     a.rho = kde_b ? rho : nullptr;
@@ -446,6 +453,7 @@ static int forces_impl(abacus_nf_cells h, const double *eps, abacus_nf_kind kind
     if (e == hipSuccess) e = launch_finalize(a, st);
     mark(h, 3, true, st);
     if (e != hipSuccess) return hip_fail(e);
+    h->amax_valid = true;
     return ABACUS_NF_OK;
 }
 
@@ -521,13 +529,6 @@ static int ensure_step_buffers(abacus_nf_cells_s *h, bool timestep) {
             if (!dalloc(h->ts_partials, need)) return ABACUS_NF_ENOMEM;
             h->ts_cap = need;
         }
-        const int64_t nref = 3 * std::max<int64_t>(h->n_cells, 1);
-        if (h->ts_ref_cap < nref) {
-            dfree(h->ts_ref);
-            h->ts_ref_cap = 0;
-            if (!dalloc(h->ts_ref, (size_t)nref)) return ABACUS_NF_ENOMEM;
-            h->ts_ref_cap = nref;
-        }
     }
     return ABACUS_NF_OK;
 }
@@ -568,32 +569,64 @@ int abacus_nf_drift(abacus_nf_cells h, const double *dt, const float *vel, float
     return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 
-int abacus_nf_timestep(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
-                       void *hip_stream) {
+static int timestep_checks(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
+                           int *dev) {
     if (!h || !dt_out || !std::isfinite(eta) || !(eta > 0)) return ABACUS_NF_EINVAL;
     if (!h->built) return ABACUS_NF_ESTATE;
-    if (h->n_total > 0 && (!vel || !acc)) return ABACUS_NF_EINVAL;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
-    if (dev != h->device) return ABACUS_NF_ESTATE;
-    int rc = ensure_step_buffers(h, true);
-    if (rc != ABACUS_NF_OK) return rc;
-    hipStream_t st = (hipStream_t)hip_stream;
-    hipError_t e = launch_timestep(vel, acc, h->keys, h->perm, h->cell_start, h->d_boxes, h->n_boxes, h->n_total,
-                                   h->n_cells, h->ts_partials, h->ts_ref, h->ts_min, dev, st);
+    if (h->n_total > 0 && !vel) return ABACUS_NF_EINVAL;
+    if (!acc && !h->amax_valid) return ABACUS_NF_ESTATE;   // no force pass since the last build
+    if (hipGetDevice(dev) != hipSuccess) return hip_fail(hipErrorUnknown);
+    if (*dev != h->device) return ABACUS_NF_ESTATE;
+    return ABACUS_NF_OK;
+}
+
+// Enqueue the criterion with the given partials and per-box minima, wait, and turn the minima into steps.
+// The minima are copied straight into dt_out (the caller's n_boxes doubles) and converted in place.
+static int timestep_run(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
+                        double *partials, unsigned long long *dmin, hipStream_t st) {
+    hipError_t e = launch_timestep(vel, acc, h->cell_amax, h->keys, h->perm, h->cell_start, h->d_boxes, h->n_boxes,
+                                   h->n_total, partials, dmin, st);
     if (e != hipSuccess) return hip_fail(e);
-    std::vector<unsigned long long> bits((size_t)h->n_boxes);
-    if (hipMemcpyAsync(bits.data(), h->ts_min, bits.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                       st) != hipSuccess ||
+    static_assert(sizeof(double) == sizeof(unsigned long long), "bit copies of doubles");
+    if (hipMemcpyAsync(dt_out, dmin, (size_t)h->n_boxes * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return hip_fail(hipErrorUnknown);
     for (int b = 0; b < h->n_boxes; b++) {
-        double r;
-        memcpy(&r, &bits[b], sizeof(double));
+        const double r = dt_out[b];   // the minimum sigma / |a|max (its bits were copied)
         dt_out[b] = std::isinf(r) ? r : eta * r;
     }
     return ABACUS_NF_OK;
 }
+
+int abacus_nf_timestep(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
+                       void *hip_stream) {
+    int dev = 0;
+    int rc = timestep_checks(h, vel, acc, eta, dt_out, &dev);
+    if (rc != ABACUS_NF_OK) return rc;
+    if ((rc = ensure_step_buffers(h, true)) != ABACUS_NF_OK) return rc;
+    return timestep_run(h, vel, acc, eta, dt_out, h->ts_partials, h->ts_min, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"
+
+namespace anf {
+
+int handle_boxes(abacus_nf_cells h) { return h ? h->n_boxes : 0; }
+
+int timestep_with_buffers(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
+                          double *partials, size_t partial_doubles, unsigned long long *dmin, int dmin_count,
+                          void *hip_stream) {
+    int dev = 0;
+    int rc = timestep_checks(h, vel, acc, eta, dt_out, &dev);
+    if (rc != ABACUS_NF_OK) return rc;
+    if (!partials || !dmin || partial_doubles < timestep_partial_doubles(h->n_total) || dmin_count < h->n_boxes)
+        return ABACUS_NF_EINVAL;
+    return timestep_run(h, vel, acc, eta, dt_out, partials, dmin, (hipStream_t)hip_stream);
+}
+
+}  // namespace anf
+
+extern "C" {
 
 int abacus_nf_reorder(abacus_nf_cells h, float *const *vec3, int32_t n_vec3, int64_t *ids, void *hip_stream) {
     if (!h || n_vec3 < 0 || n_vec3 > 64 || (n_vec3 > 0 && !vec3)) return ABACUS_NF_EINVAL;
@@ -727,6 +760,11 @@ int abacus_nf_copy_cells(abacus_nf_cells h, abacus_nf_array which, void *dst, in
         case ABACUS_NF_ARRAY_CELL_START: src = h->cell_start; want = (h->n_cells + 1) * 4; break;
         case ABACUS_NF_ARRAY_SPOS: src = h->spos; want = h->n_total * 16; break;
         case ABACUS_NF_ARRAY_CELL_KEY: src = h->keys; want = h->n_total * 4; break;
+        case ABACUS_NF_ARRAY_CELL_AMAX2:
+            if (!h->amax_valid) return ABACUS_NF_ESTATE;
+            src = h->cell_amax;
+            want = h->n_cells * 8;
+            break;
         default: return ABACUS_NF_EINVAL;
     }
     if (bytes != want) return ABACUS_NF_EINVAL;

@@ -124,16 +124,20 @@ int tune(abacus_nf_cells h, const double *eps, abacus_nf_kind kind, const double
     // ABACUS_NF_AUTOTUNE_LOG=1 prints every candidate's time to stderr
     const char *log_env = getenv("ABACUS_NF_AUTOTUNE_LOG");
     const bool log_trials = log_env && log_env[0] == '1';
+    // A candidate whose work list outgrows its capacity (ECAPACITY, reported and cleared by the sync) is
+    // skipped; any other error ends the search.
     auto trial = [&](const abacus_nf_tuning &t) -> int {
         if (abacus_nf_set_tuning(h, &t) != ABACUS_NF_OK) return ABACUS_NF_OK;  // invalid combination: skip
         int r = force_call(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream);   // warm-up (allocates if needed)
         if (r == ABACUS_NF_OK) r = abacus_nf_sync(hip_stream);
+        if (r == ABACUS_NF_ECAPACITY) return ABACUS_NF_OK;
         if (r != ABACUS_NF_OK) return r;
         hipEventRecord(e0, st);
         for (int q = 0; q < reps && r == ABACUS_NF_OK; q++)
             r = force_call(h, eps, kind, gm, mode, kde_b, acc, rho, hip_stream);
         hipEventRecord(e1, st);
         if (r == ABACUS_NF_OK) r = abacus_nf_sync(hip_stream);
+        if (r == ABACUS_NF_ECAPACITY) return ABACUS_NF_OK;
         if (r != ABACUS_NF_OK) return r;
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);

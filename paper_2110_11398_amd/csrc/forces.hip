@@ -290,9 +290,11 @@ __global__ __launch_bounds__(256) void k_wl_emit(const int32_t *__restrict__ cs,
         const int64_t base = (int64_t)ws->class_base[p.cls] + bbase[p.cls] + local;
         if (base + p.items <= item_capacity) {
             const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, (int32_t)c) : 0;
+            // part-major: consecutive items are the tiles of one source part, so the waves that take them
+            // together (one queue block goes to one XCD) stream the same sources through that XCD's L2
             int64_t k = base;
-            for (int t = 0; t < p.tiles; t++)
-                for (int q = 0; q < p.parts; q++) items[k++] = Item{(int32_t)c, t, q, b};
+            for (int q = 0; q < p.parts; q++)
+                for (int t = 0; t < p.tiles; t++) items[k++] = Item{(int32_t)c, t, q, b};
         }
     }
 }
@@ -313,6 +315,7 @@ struct KArgs {
     float *acc;
     double *acc64;  // FP64 accelerations instead of acc when not null
     float *rho;
+    unsigned long long *amax;   // [n_cells] bits of the largest |a|^2 written in each cell
     int R;
     int chunk;      // sources per LDS chunk
     int max_lanes;
@@ -346,6 +349,26 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
     s = a + b;
     const float bp = s - a;
     e = (a - (s - bp)) + (b - bp);
+}
+
+// |a|^2 of a written acceleration: FP64 squares of the stored values, each rounded, summed in a fixed order.
+__device__ inline double norm2_written(double x, double y, double z) {
+#pragma clang fp contract(off)
+    return x * x + y * y + z * z;
+}
+
+// Largest |a|^2 of a cell: the bit patterns of non-negative doubles order like their values, so an
+// integer maximum is exact and independent of the order of the updates.
+__device__ inline void cell_max(unsigned long long *amax, int c, double v) {
+    atomicMax(amax + c, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline double wave_max_f64(double v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double y = __shfl_xor(v, off);
+        v = v > y ? v : y;
+    }
+    return v;
 }
 
 // U staged sources against the S sinks of this lane.  With KDE, also the
@@ -630,6 +653,7 @@ void k_forces(KArgs a) {
             }
         }
         wave_lds_sync();
+        double amax2 = 0.0;   // largest |a|^2 this lane writes (cells written here, not split ones)
         if (sub == 0 && g < G) {
             const bool split = P > 1;
             for (int s = 0; s < S; s++) {
@@ -638,6 +662,7 @@ void k_forces(KArgs a) {
                 const int base = (g * L * S + s) * NC;
                 if (!split) {
                     const int64_t i = a.perm[cs0 + t0 + idx];
+                    double w[3];   // the values written
                     for (int d = 0; d < NC; d++) {
                         double v;   // the value before its (optional) rounding to FP32
                         if constexpr (MODE == ABACUS_NF_SUM_FP32) {
@@ -649,10 +674,18 @@ void k_forces(KArgs a) {
                             for (int q = 0; q < L; q++) t += red[base + q * S * NC + d];
                             v = d < 3 ? t * F.scale : t;
                         }
-                        if (d == 3) a.rho[i] = (float)v;
-                        else if (a.acc64) a.acc64[3 * i + d] = v;
-                        else a.acc[3 * i + d] = (float)v;
+                        if (d == 3) {
+                            a.rho[i] = (float)v;
+                        } else if (a.acc64) {
+                            a.acc64[3 * i + d] = v;
+                            w[d] = v;
+                        } else {
+                            a.acc[3 * i + d] = (float)v;
+                            w[d] = (double)(float)v;
+                        }
                     }
+                    const double m = norm2_written(w[0], w[1], w[2]);
+                    amax2 = m > amax2 ? m : amax2;
                 } else {
                     double *out = a.partials + (int64_t)NC * (a.cell_pbase[c] + (int64_t)part * nc + t0 + idx);
                     for (int d = 0; d < NC; d++) {
@@ -669,6 +702,10 @@ void k_forces(KArgs a) {
                 }
             }
         }
+        if (P <= 1) {   // per-cell maximum of |a|^2 (the input of the step-size criterion)
+            amax2 = wave_max_f64(amax2);
+            if (lane == 0 && amax2 > 0.0) cell_max(a.amax, c, amax2);
+        }
         wave_lds_sync();
     }
 }
@@ -683,33 +720,56 @@ __global__ __launch_bounds__(256) void k_finalize(const WorkState *__restrict__ 
                                                   const double *__restrict__ partials,
                                                   const BoxDev *__restrict__ boxes, int n_boxes,
                                                   const ForceBox *__restrict__ fbox, float *__restrict__ acc,
-                                                  double *__restrict__ acc64, float *__restrict__ rho, int64_t n) {
+                                                  double *__restrict__ acc64, float *__restrict__ rho,
+                                                  unsigned long long *__restrict__ amax, int64_t n) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n || ws->overflow) return;
-    const int32_t c = keys[s];
-    const int P = cell_parts[c];
-    if (P <= 1) return;
-    const int cs0 = cs[c], nc = cs[c + 1] - cs0;
-    const int64_t base = cell_pbase[c] + (s - cs0);
-    if (base + (int64_t)(P - 1) * nc >= partial_capacity) return;
-    const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, c) : 0;
-    const ForceBox F = fbox[b];
-    const int64_t i = perm[s];
-    for (int d = 0; d < NC; d++) {
-        double v;   // the value before its (optional) rounding to FP32
-        if constexpr (MODE == ABACUS_NF_SUM_FP32) {
-            float t = 0.f;
-            for (int p = 0; p < P; p++) t += (float)partials[NC * (base + (int64_t)p * nc) + d];
-            v = d < 3 ? t * F.scalef : t;
-        } else {
-            double t = 0.0;
-            for (int p = 0; p < P; p++) t += partials[NC * (base + (int64_t)p * nc) + d];
-            v = d < 3 ? t * F.scale : t;
+    if (ws->overflow) return;
+    const int lane = threadIdx.x & 63;
+    int32_t c = -1;
+    double m = 0.0;   // |a|^2 written for this slot
+    if (s < n) {
+        c = keys[s];
+        const int P = cell_parts[c];
+        const int cs0 = cs[c], nc = cs[c + 1] - cs0;
+        const int64_t base = cell_pbase[c] + (s - cs0);
+        if (P > 1 && base + (int64_t)(P - 1) * nc < partial_capacity) {
+            const int b = n_boxes > 1 ? box_of_cell(boxes, n_boxes, c) : 0;
+            const ForceBox F = fbox[b];
+            const int64_t i = perm[s];
+            double w[3];
+            for (int d = 0; d < NC; d++) {
+                double v;   // the value before its (optional) rounding to FP32
+                if constexpr (MODE == ABACUS_NF_SUM_FP32) {
+                    float t = 0.f;
+                    for (int p = 0; p < P; p++) t += (float)partials[NC * (base + (int64_t)p * nc) + d];
+                    v = d < 3 ? t * F.scalef : t;
+                } else {
+                    double t = 0.0;
+                    for (int p = 0; p < P; p++) t += partials[NC * (base + (int64_t)p * nc) + d];
+                    v = d < 3 ? t * F.scale : t;
+                }
+                if (d == 3) {
+                    rho[i] = (float)v;
+                } else if (acc64) {
+                    acc64[3 * i + d] = v;
+                    w[d] = v;
+                } else {
+                    acc[3 * i + d] = (float)v;
+                    w[d] = (double)(float)v;
+                }
+            }
+            m = norm2_written(w[0], w[1], w[2]);
         }
-        if (d == 3) rho[i] = (float)v;
-        else if (acc64) acc64[3 * i + d] = v;
-        else acc[3 * i + d] = (float)v;
     }
+    // per-cell maximum over the wave's slots: a segmented max-scan (slots are sorted by cell, so equal
+    // keys are adjacent) and one update by the last lane of each run
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(m, off);
+        const int cy = __shfl_up(c, off);
+        if (lane >= off && cy == c) m = m > y ? m : y;
+    }
+    const int cn = __shfl_down(c, 1);
+    if (c >= 0 && m > 0.0 && (lane == 63 || cn != c)) cell_max(amax, c, m);
 }
 
 // ---------------------------------------------------------------- variant dispatch
@@ -830,6 +890,7 @@ hipError_t launch_count_interactions(const ForcesArgs &a, hipStream_t st) {
 hipError_t build_work_list(const ForcesArgs &a, hipStream_t st) {
     hipError_t e = launch_count_interactions(a, st);
     if (e != hipSuccess || a.n_cells <= 0) return e;
+    if ((e = launch_fill_u64(a.amax, a.n_cells, 0ull, st)) != hipSuccess) return e;
     const int S = a.tune.sinks_per_lane, ML = a.tune.max_lanes;
     const unsigned gc = grid_for(a.n_cells, 256);
     hipLaunchKernelGGL(k_wl_plan, dim3(1), dim3(64), 0, st, a.ws, a.partial_capacity, a.item_capacity, a.n_total);
@@ -879,6 +940,7 @@ hipError_t launch_forces(const ForcesArgs &a, hipStream_t st) {
     k.acc = a.acc;
     k.acc64 = a.acc64;
     k.rho = a.rho;
+    k.amax = a.amax;
     k.R = a.R;
     k.chunk = a.tune.chunk;
     k.max_lanes = a.tune.max_lanes;
@@ -897,7 +959,7 @@ hipError_t launch_finalize(const ForcesArgs &a, hipStream_t st) {
                    : (kde ? k_finalize<ABACUS_NF_SUM_FP64, 4> : k_finalize<ABACUS_NF_SUM_FP64, 3>);
     hipLaunchKernelGGL(kfn, dim3(gn), dim3(256), 0, st, a.ws, a.partial_capacity, a.keys, a.cell_start, a.perm,
                        a.cell_parts, a.cell_pbase, a.partials, a.boxes, a.n_boxes, a.fbox, a.acc, a.acc64, a.rho,
-                       a.n_total);
+                       a.amax, a.n_total);
     return hipGetLastError();
 }
 

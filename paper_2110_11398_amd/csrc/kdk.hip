@@ -14,18 +14,19 @@
 // stored as 0 if its FP32 rounding reaches L.  Both kernels stream the arrays
 // once (HBM-bound, 36 bytes per particle each).
 //
-// Timestep: per cell, with v_ref the velocity of the cell's first particle (gathered
-// once per cell by k_ts_ref) and
+// Timestep: per cell, with v_ref the velocity of the cell's first particle and
 // d = v - v_ref, the sums S1 = sum d, S2 = sum |d|^2 and A = max |a|^2 give
 // sigma^2 = S2 / n - |S1 / n|^2 (the shift keeps the difference well
 // conditioned when the cell moves in bulk).  Cells with fewer than two
-// particles or A = 0 do not constrain the step.  The work is cut by slot like
-// the multipoles: a wave walks kTsUnit sorted slots 64 at a time, forms the five
-// sums per cell segment with a segmented scan across the wave, carries an open
-// segment into the next batch, and at a cell's end either folds sigma/|a|max
-// into a per-box minimum (atomic min on the bits of a non-negative double, so
-// exact and order-free) or, for a cell that crosses a unit boundary, writes the
-// unit's head or tail partial for k_ts_combine.
+// particles or A = 0 do not constrain the step.  The work is cut by slot: one
+// wave per kTsUnit sorted slots issues all of its loads at once, forms the
+// sums per cell segment with a segmented scan across each batch of 64 slots,
+// carries an open segment into the next batch, and at a cell's end either
+// folds sigma/|a|max into a per-box minimum (atomic min on the bits of a
+// non-negative double, so exact and order-free) or, for a cell that crosses a
+// unit boundary, writes the unit's head or tail partial for k_ts_combine.  A
+// comes either from the accelerations (gathered through the permutation) or,
+// without them, from the per-cell maxima the force pass recorded.
 //
 // Merge (Table "tbl:timing": particles are stored cell by cell): the caller's
 // per-particle arrays can be gathered into the sorted order of the last build,
@@ -38,7 +39,8 @@ namespace anf {
 namespace {
 
 constexpr int kDtChunk = 24;
-constexpr int kTsUnit = 1024;
+constexpr int kTsUnit = 256;                 // slots per wave of the timestep pass
+constexpr int kTsBatches = kTsUnit / 64;
 constexpr int kTsVals = 5;   // S1x, S1y, S1z, S2, A
 
 struct DtChunk {
@@ -52,8 +54,8 @@ __global__ void k_set_doubles(DtChunk c, double *dst) {
 }
 
 __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 __global__ __launch_bounds__(256) void k_kick(float *__restrict__ vel, const float *__restrict__ acc, int64_t n3,
@@ -113,7 +115,8 @@ __global__ __launch_bounds__(256) void k_iota_i32(int32_t *__restrict__ p, int64
 
 struct TsArgs {
     const float *vel;
-    const float *acc;
+    const float *acc;                    // accelerations, or nullptr: per-cell maxima of the force pass
+    const unsigned long long *amax;      // [n_cells] bits of max |a|^2 per cell (used when acc is nullptr)
     const int32_t *keys;
     const int32_t *perm;
     const int32_t *cs;
@@ -122,207 +125,211 @@ struct TsArgs {
     int64_t n;
     double *partials;             // [2 per unit][kTsVals]: head, tail
     unsigned long long *dmin;     // [n_boxes] bits of the smallest sigma / |a|max
-    const float *ref;             // [n_cells][3] velocity of each occupied cell's first particle
 };
 
-// Reference velocity of every occupied cell: the velocity of its first sorted particle (read once per cell,
-// so the per-particle pass below has no chain of dependent lookups for it).
-__global__ __launch_bounds__(256) void k_ts_ref(const float *__restrict__ vel, const int32_t *__restrict__ perm,
-                                                const int32_t *__restrict__ cs, int64_t n_cells,
-                                                float *__restrict__ ref) {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int s0 = cs[c];
-        if (cs[c + 1] > s0) {
-            const int64_t r = perm[s0];
-            ref[3 * c + 0] = vel[3 * r + 0];
-            ref[3 * c + 1] = vel[3 * r + 1];
-            ref[3 * c + 2] = vel[3 * r + 2];
-        }
-    }
+// |x|^2 with every product and sum rounded on its own, in a fixed order (the same value the caller gets
+// from (x*x + y*y) + z*z in FP64).
+__device__ inline double norm2(double x, double y, double z) {
+#pragma clang fp contract(off)
+    return x * x + y * y + z * z;
 }
 
-__device__ inline double cell_ratio(const double *t, int n) {
+__device__ inline double cell_ratio(const double *t, int n, double A) {
     // sigma / |a|max, or a negative value when the cell does not constrain the step
-    if (n < 2 || !(t[4] > 0.0)) return -1.0;
+    if (n < 2 || !(A > 0.0)) return -1.0;
     const double inv = 1.0 / n;
     const double m2 = (t[0] * t[0] + t[1] * t[1] + t[2] * t[2]) * inv * inv;
     double s2 = t[3] * inv - m2;
     s2 = s2 > 0.0 ? s2 : 0.0;
-    return sqrt(s2) / sqrt(t[4]);
+    return sqrt(s2) / sqrt(A);
 }
 
 __device__ inline void fold_min(unsigned long long *dmin, int box, double r) {
     atomicMin(dmin + box, (unsigned long long)__double_as_longlong(r));
 }
 
-__global__ __launch_bounds__(64) void k_ts_units(TsArgs a) {
-    const int lane = threadIdx.x;
+// One wave per unit of kTsUnit sorted slots.  Every load of the unit is issued before the first sum: keys
+// and permutation entries (coalesced), then the velocities (and accelerations) gathered through the
+// permutation.  The unit is reduced in batches of 64 slots.  The shift of a cell is the velocity of its
+// first particle: a lane takes it from the lane where its cell starts in the batch, or from the segment
+// still open at the end of the previous batch, or, for a cell that began before the unit, from one
+// wave-uniform lookup.
+template <bool FUSED>
+__global__ __launch_bounds__(256) void k_ts_units(TsArgs a) {
+    constexpr int NV = FUSED ? 4 : kTsVals;   // components of the scan (A comes from the force pass)
+    const int lane = threadIdx.x & 63;
     const int64_t n_units = (a.n + kTsUnit - 1) / kTsUnit;
-    const unsigned G = gridDim.x;
-    const unsigned per_xcd = G / kQueues;
-    const unsigned vb = (blockIdx.x % kQueues) * per_xcd + blockIdx.x / kQueues;
-    const int64_t chunk = (n_units + G - 1) / G;
-    const int64_t u_begin = (int64_t)vb * chunk;
-    const int64_t u_end = u_begin + chunk < n_units ? u_begin + chunk : n_units;
+    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u >= n_units) return;
+    const int64_t s0 = u * kTsUnit;
+    const int64_t s1 = s0 + kTsUnit < a.n ? s0 + kTsUnit : a.n;
+    int key[kTsBatches];
+    float v[kTsBatches][3], g[kTsBatches][3];
+#pragma unroll
+    for (int b = 0; b < kTsBatches; b++) {
+        const int64_t s = s0 + 64 * b + lane;
+        key[b] = s < s1 ? a.keys[s] : -2;
+        const int64_t p = s < s1 ? a.perm[s] : 0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            v[b][d] = s < s1 ? a.vel[3 * p + d] : 0.f;
+            g[b][d] = (!FUSED && s < s1) ? a.acc[3 * p + d] : 0.f;
+        }
+    }
+    const int unit_prev = s0 > 0 ? a.keys[s0 - 1] : -1;
+    const int after = s1 < a.n ? a.keys[s1] : -1;
+    float carry_ref[3] = {0.f, 0.f, 0.f};
+    {
+        const int k0 = __builtin_amdgcn_readfirstlane(key[0]);
+        if (k0 == unit_prev) {   // the unit starts inside a cell: its first particle lies before the unit
+            const int64_t pf = a.perm[a.cs[k0]];
+#pragma unroll
+            for (int d = 0; d < 3; d++) carry_ref[d] = a.vel[3 * pf + d];
+        }
+    }
+    double carry[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int carry_key = -1;
     int lane_box = -1;
     double lane_min = 0.0;
-    for (int64_t u = u_begin; u < u_end; u++) {
-        const int64_t s0 = u * kTsUnit;
-        const int64_t s1 = s0 + kTsUnit < a.n ? s0 + kTsUnit : a.n;
-        const int unit_prev = s0 > 0 ? a.keys[s0 - 1] : -1;
-        const int after = s1 < a.n ? a.keys[s1] : -1;
-        double carry[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        int carry_key = -1;
-        // two-deep pipeline: while a batch is reduced, the velocities, accelerations and reference velocities
-        // of the next batch are in flight (gathered through the permutation), and the keys and permutation
-        // entries of the batch after it
-        int key_n = s0 + lane < s1 ? a.keys[s0 + lane] : -2;
-        int perm_n = s0 + lane < s1 ? a.perm[s0 + lane] : 0;
-        float v_n[3] = {0.f, 0.f, 0.f}, g_n[3] = {0.f, 0.f, 0.f}, r_n[3] = {0.f, 0.f, 0.f};
-        if (s0 + lane < s1) {
-            const float *vr = a.ref + 3 * (int64_t)key_n;
 #pragma unroll
-            for (int d = 0; d < 3; d++) {
-                v_n[d] = a.vel[3 * (int64_t)perm_n + d];
-                g_n[d] = a.acc[3 * (int64_t)perm_n + d];
-                r_n[d] = vr[d];
+    for (int b = 0; b < kTsBatches; b++) {
+        const int64_t b0 = s0 + 64 * b;
+        if (b0 >= s1) break;
+        const int nb = (int)(s1 - b0 < 64 ? s1 - b0 : 64);
+        const bool live = lane < nb;
+        const int k = key[b];
+        const int up = __shfl_up(k, 1);
+        const int before = b == 0 ? unit_prev : __shfl(key[b > 0 ? b - 1 : 0], 63);
+        const bool start = live && k != (lane == 0 ? before : up);   // the first slot of its cell
+        const unsigned long long startmask = __ballot(start);
+        const unsigned long long below = startmask & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+        const int sl = below ? 63 - __builtin_clzll(below) : 0;
+        float r[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const float t = __shfl(v[b][d], sl);
+            r[d] = below ? t : carry_ref[d];
+        }
+        int nxt = __shfl_down(k, 1);
+        if (lane == nb - 1) nxt = (b0 + 64 < s1) ? __shfl(key[b + 1 < kTsBatches ? b + 1 : b], 0) : ~k;
+        const bool end = live && k != nxt;
+        const unsigned long long endmask = __ballot(end);
+        double x[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (live) {
+            const double dx = (double)v[b][0] - (double)r[0];
+            const double dy = (double)v[b][1] - (double)r[1];
+            const double dz = (double)v[b][2] - (double)r[2];
+            x[0] = dx;
+            x[1] = dy;
+            x[2] = dz;
+            x[3] = norm2(dx, dy, dz);
+            if (!FUSED) x[4] = norm2((double)g[b][0], (double)g[b][1], (double)g[b][2]);
+        }
+        // segmented inclusive scan over the lanes of the batch (sums, and a max for A)
+        bool f = lane == 0 || k != up;
+        for (int off = 1; off < 64; off <<= 1) {
+            double y[kTsVals];
+#pragma unroll
+            for (int q = 0; q < NV; q++) y[q] = __shfl_up(x[q], off);
+            const bool fy = __shfl_up((int)f, off) != 0;
+            if (lane >= off) {
+                if (!f) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) x[q] += y[q];
+                    if (!FUSED) x[4] = x[4] > y[4] ? x[4] : y[4];
+                }
+                f = f || fy;
             }
         }
-        int key_nn = s0 + 64 + lane < s1 ? a.keys[s0 + 64 + lane] : -2;
-        int perm_nn = s0 + 64 + lane < s1 ? a.perm[s0 + 64 + lane] : 0;
-        for (int64_t b0 = s0; b0 < s1; b0 += 64) {
-            const int nb = (int)(s1 - b0 < 64 ? s1 - b0 : 64);
-            const bool live = lane < nb;
-            const int key = key_n;
-            float v[3], g[3], r[3];
+        const int c0 = __builtin_amdgcn_readfirstlane(k);
+        const bool add_carry = carry_key >= 0 && c0 == carry_key;
+        const int e0 = endmask ? __builtin_ctzll(endmask) : -1;
+        if (end) {
+            if (lane == e0 && add_carry) {
 #pragma unroll
-            for (int d = 0; d < 3; d++) {
-                v[d] = v_n[d];
-                g[d] = g_n[d];
-                r[d] = r_n[d];
+                for (int q = 0; q < 4; q++) x[q] += carry[q];
+                if (!FUSED) x[4] = x[4] > carry[4] ? x[4] : carry[4];
             }
-            const int64_t b1 = b0 + 64, b2 = b0 + 128;
-            const bool live_n = b1 + lane < s1;
-            key_n = key_nn;
-            perm_n = perm_nn;
-            if (live_n) {
-                const float *vr = a.ref + 3 * (int64_t)key_n;
-#pragma unroll
-                for (int d = 0; d < 3; d++) {
-                    v_n[d] = a.vel[3 * (int64_t)perm_n + d];
-                    g_n[d] = a.acc[3 * (int64_t)perm_n + d];
-                    r_n[d] = vr[d];
-                }
-            }
-            key_nn = b2 + lane < s1 ? a.keys[b2 + lane] : -2;
-            perm_nn = b2 + lane < s1 ? a.perm[b2 + lane] : 0;
-            const int first_next = __builtin_amdgcn_readfirstlane(key_n);   // cell of slot b1 when b1 < s1
-            const int prevk = __shfl_up(key, 1);
-            int nxt = __shfl_down(key, 1);
-            if (lane == nb - 1) nxt = (b1 < s1) ? first_next : ~key;       // the unit's end closes a segment
-            const bool end = live && key != nxt;
-            const uint64_t endmask = __ballot(end);
-            double x[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            if (live) {
-                const double dx = (double)v[0] - (double)r[0];
-                const double dy = (double)v[1] - (double)r[1];
-                const double dz = (double)v[2] - (double)r[2];
-                const double ax = g[0], ay = g[1], az = g[2];
-                x[0] = dx;
-                x[1] = dy;
-                x[2] = dz;
-                x[3] = dx * dx + dy * dy + dz * dz;
-                x[4] = ax * ax + ay * ay + az * az;
-            }
-            // segmented inclusive scan over the lanes (sums, and a max for A)
-            bool f = lane == 0 || key != prevk;
-            for (int off = 1; off < 64; off <<= 1) {
-                double y[kTsVals];
-#pragma unroll
-                for (int k = 0; k < kTsVals; k++) y[k] = __shfl_up(x[k], off);
-                const bool fy = __shfl_up((int)f, off) != 0;
-                if (lane >= off) {
-                    if (!f) {
-#pragma unroll
-                        for (int k = 0; k < 4; k++) x[k] += y[k];
-                        x[4] = x[4] > y[4] ? x[4] : y[4];
+            const bool started = k != unit_prev;
+            const bool ends = (b0 + lane + 1 < s1) || after != k;
+            if (started && ends) {
+                const double A = FUSED ? __longlong_as_double((long long)a.amax[k]) : x[4];
+                const double rr = cell_ratio(x, a.cs[k + 1] - a.cs[k], A);
+                if (rr >= 0.0) {
+                    const int bx = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, k) : 0;
+                    if (bx != lane_box) {
+                        if (lane_box >= 0) fold_min(a.dmin, lane_box, lane_min);
+                        lane_box = bx;
+                        lane_min = rr;
+                    } else {
+                        lane_min = rr < lane_min ? rr : lane_min;
                     }
-                    f = f || fy;
                 }
-            }
-            const int c0 = __builtin_amdgcn_readfirstlane(key);
-            const bool add_carry = carry_key >= 0 && c0 == carry_key;
-            const int e0 = endmask ? __builtin_ctzll(endmask) : -1;
-            if (end) {
-                if (lane == e0 && add_carry) {
-#pragma unroll
-                    for (int k = 0; k < 4; k++) x[k] += carry[k];
-                    x[4] = x[4] > carry[4] ? x[4] : carry[4];
-                }
-                const bool started = key != unit_prev;
-                const bool ends = (b0 + lane + 1 < s1) || after != key;
-                if (started && ends) {
-                    const double r = cell_ratio(x, a.cs[key + 1] - a.cs[key]);
-                    if (r >= 0.0) {
-                        const int bx = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, key) : 0;
-                        if (bx != lane_box) {
-                            if (lane_box >= 0) fold_min(a.dmin, lane_box, lane_min);
-                            lane_box = bx;
-                            lane_min = r;
-                        } else {
-                            lane_min = r < lane_min ? r : lane_min;
-                        }
-                    }
-                } else {
-                    double *o = a.partials + (2 * u + (started ? 1 : 0)) * kTsVals;
-#pragma unroll
-                    for (int k = 0; k < kTsVals; k++) o[k] = x[k];
-                }
-            }
-            // the segment still open at the batch's end becomes the carry
-            if (!((endmask >> (nb - 1)) & 1)) {
-                double t[kTsVals];
-#pragma unroll
-                for (int k = 0; k < kTsVals; k++) t[k] = __shfl(x[k], nb - 1);
-                if (endmask == 0 && add_carry) {
-#pragma unroll
-                    for (int k = 0; k < 4; k++) t[k] += carry[k];
-                    t[4] = t[4] > carry[4] ? t[4] : carry[4];
-                }
-#pragma unroll
-                for (int k = 0; k < kTsVals; k++) carry[k] = t[k];
-                carry_key = __shfl(key, nb - 1);
             } else {
-                carry_key = -1;
+                double *o = a.partials + (2 * u + (started ? 1 : 0)) * kTsVals;
+#pragma unroll
+                for (int q = 0; q < kTsVals; q++) o[q] = x[q];
             }
+        }
+        // the segment still open at the batch's end becomes the carry (with its shift)
+        if (!((endmask >> (nb - 1)) & 1)) {
+            double t[kTsVals];
+#pragma unroll
+            for (int q = 0; q < kTsVals; q++) t[q] = __shfl(x[q], nb - 1);
+            if (endmask == 0 && add_carry) {
+#pragma unroll
+                for (int q = 0; q < 4; q++) t[q] += carry[q];
+                t[4] = t[4] > carry[4] ? t[4] : carry[4];
+            }
+#pragma unroll
+            for (int q = 0; q < kTsVals; q++) carry[q] = t[q];
+            carry_key = __shfl(k, nb - 1);
+#pragma unroll
+            for (int d = 0; d < 3; d++) carry_ref[d] = __shfl(r[d], nb - 1);
+        } else {
+            carry_key = -1;
         }
     }
     if (lane_box >= 0) fold_min(a.dmin, lane_box, lane_min);
 }
 
-// Cells that cross unit boundaries: the tail partial of the unit where the cell begins and the head
-// partials of the units it continues into (sums added, maxima taken), then the ratio.
-__global__ __launch_bounds__(64) void k_ts_combine(TsArgs a) {
+// Cells that cross unit boundaries, one wave per boundary: at the first boundary a cell crosses, the
+// lanes add the head partials of the units it continues into (lane l takes units u + l, u + l + 64, ...),
+// a fixed butterfly combines the lanes, and lane 0 adds the tail partial of the unit where the cell begins.
+// Fixed orders throughout, so the result does not depend on scheduling.
+template <bool FUSED>
+__global__ __launch_bounds__(256) void k_ts_combine(TsArgs a) {
+    const int lane = threadIdx.x & 63;
     const int64_t n_units = (a.n + kTsUnit - 1) / kTsUnit;
-    for (int64_t u = 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_units;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const int c = a.keys[u * kTsUnit];
-        if (a.keys[u * kTsUnit - 1] != c) continue;
-        if (u >= 2 && a.keys[(u - 1) * kTsUnit - 1] == c) continue;
-        double t[kTsVals];
+    const int64_t u = 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u >= n_units) return;
+    const int c = a.keys[u * kTsUnit];
+    if (a.keys[u * kTsUnit - 1] != c) return;
+    if (u >= 2 && a.keys[(u - 1) * kTsUnit - 1] == c) return;
+    const int64_t last = (a.cs[c + 1] - 1) / kTsUnit;   // unit of the cell's last slot
+    double t[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t w = u + lane; w <= last; w += 64) {
+        const double *h = a.partials + (2 * w) * kTsVals;
 #pragma unroll
-        for (int k = 0; k < kTsVals; k++) t[k] = a.partials[(2 * (u - 1) + 1) * kTsVals + k];
-        const int64_t last = (a.cs[c + 1] - 1) / kTsUnit;   // unit of the cell's last slot
-        for (int64_t v = u; v <= last; v++) {
-            const double *h = a.partials + (2 * v) * kTsVals;
-#pragma unroll
-            for (int k = 0; k < 4; k++) t[k] += h[k];
-            t[4] = t[4] > h[4] ? t[4] : h[4];
-        }
-        const double r = cell_ratio(t, a.cs[c + 1] - a.cs[c]);
-        if (r >= 0.0) fold_min(a.dmin, a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, c) : 0, r);
+        for (int q = 0; q < 4; q++) t[q] += h[q];
+        if (!FUSED) t[4] = t[4] > h[4] ? t[4] : h[4];
     }
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) t[q] += __shfl_xor(t[q], off);
+        if (!FUSED) {
+            const double y = __shfl_xor(t[4], off);
+            t[4] = t[4] > y ? t[4] : y;
+        }
+    }
+    if (lane != 0) return;
+    const double *tail = a.partials + (2 * (u - 1) + 1) * kTsVals;
+    double s[kTsVals];
+#pragma unroll
+    for (int q = 0; q < 4; q++) s[q] = tail[q] + t[q];
+    const double A = FUSED ? __longlong_as_double((long long)a.amax[c]) : (tail[4] > t[4] ? tail[4] : t[4]);
+    const double r = cell_ratio(s, a.cs[c + 1] - a.cs[c], A);
+    if (r >= 0.0) fold_min(a.dmin, a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, c) : 0, r);
 }
 
 int grid_of(int64_t n, int threads, int device, int per_cu) {
@@ -390,9 +397,16 @@ size_t timestep_partial_doubles(int64_t n) {
     return (size_t)(2 * (units > 0 ? units : 1)) * kTsVals;
 }
 
-hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *keys, const int32_t *perm,
-                           const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, int64_t n_cells,
-                           double *partials, float *ref, unsigned long long *dmin, int device, hipStream_t st) {
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_timestep(const float *vel, const float *acc, const unsigned long long *amax, const int32_t *keys,
+                           const int32_t *perm, const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n,
+                           double *partials, unsigned long long *dmin, hipStream_t st) {
     const unsigned long long inf_bits = 0x7FF0000000000000ull;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n_boxes + 255) / 256)), dim3(256), 0, st, dmin,
                        (int64_t)n_boxes, inf_bits);
@@ -401,6 +415,7 @@ hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *ke
     TsArgs a;
     a.vel = vel;
     a.acc = acc;
+    a.amax = amax;
     a.keys = keys;
     a.perm = perm;
     a.cs = cs;
@@ -409,19 +424,13 @@ hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *ke
     a.n = n;
     a.partials = partials;
     a.dmin = dmin;
-    a.ref = ref;
-    hipLaunchKernelGGL(k_ts_ref, dim3((unsigned)grid_of(n_cells, 256, device, 32)), dim3(256), 0, st, vel, perm, cs,
-                       n_cells, ref);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    int cus = 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
     const int64_t n_units = (n + kTsUnit - 1) / kTsUnit;
-    int64_t grid = std::min<int64_t>(n_units, (int64_t)cus * 32);
-    grid = (grid + kQueues - 1) / kQueues * kQueues;
-    hipLaunchKernelGGL(k_ts_units, dim3((unsigned)grid), dim3(64), 0, st, a);
+    const bool fused = acc == nullptr;
+    hipLaunchKernelGGL(fused ? k_ts_units<true> : k_ts_units<false>, dim3((unsigned)((n_units + 3) / 4)), dim3(256),
+                       0, st, a);
     if ((e = hipGetLastError()) != hipSuccess || n_units < 2) return e;
-    const int64_t cgrid = std::min<int64_t>((n_units + 63) / 64, (int64_t)cus * 4);
-    hipLaunchKernelGGL(k_ts_combine, dim3((unsigned)cgrid), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(fused ? k_ts_combine<true> : k_ts_combine<false>, dim3((unsigned)((n_units - 1 + 3) / 4)),
+                       dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

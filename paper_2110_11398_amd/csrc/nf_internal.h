@@ -218,6 +218,7 @@ struct ForcesArgs {
     float *acc;
     double *acc64;   // FP64 accelerations instead of acc (nullptr: FP32 output)
     float *rho;      // density output (nullptr: forces only)
+    unsigned long long *amax;   // [n_cells] bits of the largest |a|^2 written in each cell (FP64)
     int *err;
     abacus_nf_kind kind;
     abacus_nf_sum mode;
@@ -243,8 +244,17 @@ hipError_t launch_drift(float *pos, const float *vel, int64_t n, const BoxDev *b
 hipError_t launch_reorder(float *const *vec3, int n_vec3, int64_t *ids, int32_t *perm, int64_t n, void *scratch,
                           int device, hipStream_t st);
 size_t timestep_partial_doubles(int64_t n);
-hipError_t launch_timestep(const float *vel, const float *acc, const int32_t *keys, const int32_t *perm,
-                           const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n, int64_t n_cells,
-                           double *partials, float *ref, unsigned long long *dmin, int device, hipStream_t st);
+hipError_t launch_timestep(const float *vel, const float *acc, const unsigned long long *amax, const int32_t *keys,
+                           const int32_t *perm, const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n,
+                           double *partials, unsigned long long *dmin, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
+
+// The step-size criterion of a handle with buffers the caller provides (api.hip): partials of at least
+// timestep_partial_doubles(n_total) doubles and per-box minima of at least n_boxes entries.  The argument
+// checks of abacus_nf_timestep come first; EINVAL when a buffer is missing or too small.
+int timestep_with_buffers(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
+                          double *partials, size_t partial_doubles, unsigned long long *dmin, int dmin_count,
+                          void *hip_stream);
+int handle_boxes(abacus_nf_cells h);   // boxes of a handle (0 for NULL)
 
 }  // namespace anf

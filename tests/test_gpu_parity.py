@@ -590,6 +590,57 @@ def test_work_list_overflow_is_reported(nf):
     c.free()
 
 
+def _tile_count(n, S, ml):
+    """Tiles of a cell of n sinks under the work list's cut (whole 64-group tiles, then the binary cut of the
+    rest), for sizing a work-list capacity in the autotuner test."""
+    g = -(-n // S)
+    count, r = g // 64, g % 64
+    while r > 0:
+        count += 1
+        L0 = min(64 // r, ml)
+        k = 1 << (r.bit_length() - 1)
+        if k == r or 8 * r * L0 >= 7 * 64 or 64 // k > ml:
+            break
+        r -= k
+    return count
+
+
+def test_autotune_search_writes_the_cache_and_skips_overflowing_candidates(nf, tmp_path):
+    """The autotuner's search on an empty cache: a work-list capacity that only the S = 4 tiles fit makes every
+    S = 1 and S = 2 candidate overflow (skipped, not fatal); the search keeps an S = 4 tuning, records it under
+    its key, its forces match the oracle, and a second call takes the tuning from the cache."""
+    import json
+    rng = np.random.default_rng(23)
+    K = 5
+    heavy = (np.array([2.5, 1.5, 3.5]) / K + 0.03 * (rng.random((1000, 3)) - 0.5) / K)
+    lone = (np.array([(i // 25, (i // 5) % 5, i % 5) for i in range(125) if i != 2 * 25 + 1 * 5 + 3][:100]) + 0.5) / K
+    pos = np.concatenate([heavy, lone]).astype(np.float32)
+    counts = np.bincount(oracle.bin_cells(pos, 1.0, K), minlength=K ** 3)
+    need = {(S, ml): sum(_tile_count(int(n), S, ml) for n in counts if n > 0) for S in (1, 2, 4) for ml in (4, 16, 64)}
+    cap = max(need[(4, ml)] for ml in (4, 16, 64))
+    assert all(need[(S, ml)] > cap for S in (1, 2) for ml in (4, 16, 64)), need
+    p = torch.from_numpy(pos).cuda()
+    c = nf.build_cells(p, [(len(pos), 1.0, K)], 2)
+    c.set_tuning(item_capacity=cap)
+    cache = tmp_path / "cache.json"
+    eps, gm = [0.2 / K], [1.0 / len(pos)]
+    acc = torch.empty((len(pos), 3), dtype=torch.float32, device="cuda")
+    t = c.autotune(eps, gm, SPLINE, 1, acc, reps=1, cache_path=str(cache))
+    nf.sync()
+    assert t.sinks_per_lane == 4 and t.item_capacity == cap, t.as_dict()
+    table = json.loads(cache.read_text())
+    assert len(table) == 1
+    key, val = next(iter(table.items()))
+    assert "|k0|m1|" in key and val[0] == 4, table
+    ref, mag = oracle.forces(pos, 1.0, K, 2, eps[0], SPLINE, gm[0], return_mag=True)
+    check(acc.cpu().numpy().astype(np.float64), ref, mag, "autotuned forces")
+    c.reset_tuning()
+    c.set_tuning(item_capacity=cap)
+    t2 = c.autotune(eps, gm, SPLINE, 1, acc, reps=1, cache_path=str(cache))
+    assert t2.as_dict() == t.as_dict()
+    c.free()
+
+
 def test_bad_tuning_is_rejected(nf):
     p = torch.rand((100, 3), device="cuda")
     c = nf.build_cells(p, [(100, 1.0, 5)], 2)
@@ -998,6 +1049,129 @@ def test_timestep_heavy_cells_bulk_flow_and_lone_particles(nf):
                      torch.from_numpy(np.concatenate([a1, a2])).cuda(), 0.25)
     ref = [okdk.cell_timestep(p1, v1, a1, 1.0, K, 0.25), okdk.cell_timestep(p2, v2, a2, 1.0, 8, 0.25)]
     _ts_check(got, ref, "timestep heavy / bulk / lone")
+    c.free()
+
+
+def test_timestep_each_heavy_cell_limits_in_turn(nf):
+    """Each cell in turn made the limiting one (its accelerations scaled by 100): cells that cross several
+    256-slot units (1000, 2049 and 5000 particles), a cell whose slots start in the middle of a 64-slot batch,
+    and background cells; both the gathered accelerations and a bulk flow 10^4 times the dispersion."""
+    rng = np.random.default_rng(5)
+    K = 6
+    cen = (np.array([[1, 2, 3], [4, 4, 4], [0, 5, 1], [3, 0, 2]]) + 0.5) / K
+    parts = [c + 0.02 * rng.standard_normal((n, 3)) for c, n in zip(cen, (1000, 2049, 5000, 37))]
+    pos = (np.concatenate(parts + [rng.random((300, 3))]) % 1.0).astype(np.float32)
+    vel = (100.0 + 1e-2 * rng.standard_normal(pos.shape)).astype(np.float32)
+    acc = rng.standard_normal(pos.shape).astype(np.float32)
+    cells_of = oracle.bin_cells(pos, 1.0, K)
+    counts = np.bincount(cells_of, minlength=K ** 3)
+    start = np.concatenate([[0], np.cumsum(counts)])
+    targets = [int(cells_of[0]), int(cells_of[1000]), int(cells_of[3049]), int(cells_of[8049])]
+    targets += [int(c) for c in np.flatnonzero(counts >= 2)[:40] if c not in targets][:6]
+    assert any(start[t] % 64 != 0 for t in targets)
+    c = nf.build_cells(torch.from_numpy(pos).cuda(), [(len(pos), 1.0, K)], 2)
+    v = torch.from_numpy(vel).cuda()
+    base = okdk.cell_timestep(pos, vel, acc, 1.0, K, 0.25)
+    for t in targets:
+        a2 = acc.copy()
+        a2[cells_of == t] *= 100
+        ref = okdk.cell_timestep(pos, vel, a2, 1.0, K, 0.25)
+        got = c.timestep(v, torch.from_numpy(a2).cuda(), 0.25)
+        _ts_check(got, [ref], f"timestep, cell {t} ({counts[t]} particles, first slot {start[t]}) limiting")
+        assert ref < base
+    c.free()
+
+
+def _cell_amax(nf, c):
+    """Largest |a| of every cell as recorded by the last force pass."""
+    return np.sqrt(c.copy(nf.ARRAY_CELL_AMAX2).cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_cell_max_accel_recorded_by_the_force_pass(nf, mode):
+    """The force pass records, per cell, the largest |a| it wrote: bit for bit the oracle's per-cell maximum
+    of the written FP32 accelerations, in cells written directly and in cells whose source list is split
+    (finalized separately), over a batch of boxes."""
+    w = gen.workload("batched", n_boxes=3, lo=24 ** 3, hi=40 ** 3, seed=31)
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    eps, gm = [b.eps for b in w.boxes], [b.gm for b in w.boxes]
+    for tuning in (None, dict(part_sources=1024, max_lanes=4)):
+        acc, c = run(nf, w.concat_positions(), boxes, eps, gm, SPLINE, mode, tuning=tuning)
+        got = _cell_amax(nf, c)
+        off, base = 0, 0
+        for b in w.boxes:
+            ref = okdk.cell_max_accel(b.pos, acc[off:off + b.n].astype(np.float32), b.box, b.K)
+            assert np.array_equal(got[base:base + b.K ** 3], ref), (mode, tuning, b.n)
+            off += b.n
+            base += b.K ** 3
+        c.free()
+
+
+def test_cell_max_accel_of_the_f64_output(nf):
+    """With FP64 output the maxima are those of the unrounded accelerations (within FP32 rounding of the
+    FP32 output's maxima) and track the output of the call."""
+    w = gen.workload("clustered", side=32, K=8, n_halos=24)
+    b = w.boxes[0]
+    pos = torch.from_numpy(b.pos).cuda()
+    c = nf.build_cells(pos, [(b.n, b.box, b.K)], 2)
+    c.set_tuning(part_sources=1024)
+    a64 = c.forces_f64([b.eps], [b.gm], SPLINE, 1)
+    got = _cell_amax(nf, c)
+    a32 = c.forces([b.eps], [b.gm], SPLINE, 1).cpu().numpy()
+    ref = okdk.cell_max_accel(b.pos, a32, b.box, b.K)
+    got32 = _cell_amax(nf, c)
+    nf.sync()
+    assert np.array_equal(got32, ref)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -23 * ref)
+    cells = oracle.bin_cells(b.pos, b.box, b.K)
+    a64 = a64.cpu().numpy()
+    for k in np.flatnonzero(np.bincount(cells, minlength=b.K ** 3))[:50]:
+        assert got[k] == np.sqrt((a64[cells == k] ** 2).sum(axis=1)).max()
+    c.free()
+
+
+def test_timestep_from_the_force_pass_maxima(nf):
+    """acc = NULL: max |a| per cell comes from the last force pass; the step equals the one computed from
+    the gathered accelerations bit for bit and the oracle's to 1e-9; before any force pass on a new build the
+    call is refused."""
+    w = gen.workload("batched", n_boxes=3, lo=20 ** 3, hi=36 ** 3, seed=8)
+    boxes = [(b.n, b.box, b.K) for b in w.boxes]
+    eps, gm = [b.eps for b in w.boxes], [b.gm for b in w.boxes]
+    pos = w.concat_positions()
+    rng = np.random.default_rng(9)
+    vel = (1e-3 * rng.standard_normal(pos.shape)).astype(np.float32)
+    acc, c = run(nf, pos, boxes, eps, gm, SPLINE, 1, tuning=dict(part_sources=1024))
+    v = torch.from_numpy(vel).cuda()
+    fused = c.timestep(v, None, 0.25)
+    gathered = c.timestep(v, torch.from_numpy(acc.astype(np.float32)).cuda(), 0.25)
+    assert fused == gathered
+    ref, off = [], 0
+    for b in w.boxes:
+        ref.append(okdk.cell_timestep(b.pos, vel[off:off + b.n], acc[off:off + b.n].astype(np.float32), b.box,
+                                      b.K, 0.25))
+        off += b.n
+    _ts_check(fused, ref, "timestep from the force pass")
+    nf.build_cells(torch.from_numpy(pos).cuda(), boxes, 2, cells=c)
+    with pytest.raises(nf.NearFieldError):
+        c.timestep(v, None, 0.25)
+    with pytest.raises(nf.NearFieldError):
+        c.copy(nf.ARRAY_CELL_AMAX2)
+    c.free()
+
+
+def test_timestep_clustered_full_size(nf, clustered_full, tmp_path):
+    """The clustered workload at full size in the benchmark's launch configuration: the step from the force
+    pass maxima and from the gathered accelerations, against the oracle's."""
+    b = clustered_full
+    acc, c, t = run_bench_config(nf, b.pos, [(b.n, b.box, b.K)], [b.eps], [b.gm], SPLINE, 1, tmp_path)
+    rng = np.random.default_rng(11)
+    vel = (1e-3 * rng.standard_normal(b.pos.shape)).astype(np.float32)
+    v = torch.from_numpy(vel).cuda()
+    fused = c.timestep(v, None, 0.25)
+    gathered = c.timestep(v, acc, 0.25)
+    assert fused == gathered
+    ref = okdk.cell_timestep(b.pos, vel, acc.cpu().numpy(), b.box, b.K, 0.25)
+    _ts_check(fused, [ref], "timestep clustered full size")
     c.free()
 
 

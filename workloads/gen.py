@@ -220,8 +220,9 @@ def _log_uniform_scale(lo: float, hi: float) -> Callable:
 def _late(seed: int = 5, n: int = 2 ** 27, K: int = 256, n_halos: int = 16384) -> Workload:
     pos = _clustered_box(seed, n, K, 0.5, n_halos, _log_uniform_scale(0.05, 0.5))
     sp = 1.0 / n ** (1.0 / 3.0)
+    size = f"2^{n.bit_length() - 1}" if n & (n - 1) == 0 else str(n)
     return Workload("late", [Box(pos, 1.0, K, sp / 40.0, 1.0 / n, seed)],
-                    description=f"N=2^27, K={K}, 50% in {n_halos} Plummer halos with scale radius "
+                    description=f"N={size}, K={K}, 50% in {n_halos} Plummer halos with scale radius "
                                 "log-uniform in [0.05,0.5] cell, eps=spacing/40, G*m=1/N")
 
 
