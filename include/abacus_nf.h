@@ -234,7 +234,8 @@ int abacus_nf_drift(abacus_nf_cells cells, const double *dt, const float *vel, f
  *   acc     device float32 [n_total][3], input order; or NULL to take max |a_j|
  *           of each cell from the last forces call on this handle since its
  *           last build (the force pass records the largest |a|^2 it writes in
- *           each cell; ESTATE if there was no such call).  Accelerations
+ *           each cell; ESTATE if there was no such call and the batch has
+ *           particles).  Accelerations
  *           changed after that call (a far-field co-add) are not seen then.
  *   eta     > 0 (AbacusSummit uses 0.25).
  *   dt_out  host double [n_boxes].

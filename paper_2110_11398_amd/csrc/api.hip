@@ -569,12 +569,19 @@ int abacus_nf_drift(abacus_nf_cells h, const double *dt, const float *vel, float
     return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 
-static int timestep_checks(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
-                           int *dev) {
+static int timestep_args(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out) {
     if (!h || !dt_out || !std::isfinite(eta) || !(eta > 0)) return ABACUS_NF_EINVAL;
     if (!h->built) return ABACUS_NF_ESTATE;
     if (h->n_total > 0 && !vel) return ABACUS_NF_EINVAL;
-    if (!acc && !h->amax_valid) return ABACUS_NF_ESTATE;   // no force pass since the last build
+    // without accelerations the maxima of a force pass since the last build are needed (none for no particles)
+    if (!acc && !h->amax_valid && h->n_total > 0) return ABACUS_NF_ESTATE;
+    return ABACUS_NF_OK;
+}
+
+static int timestep_checks(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
+                           int *dev) {
+    const int rc = timestep_args(h, vel, acc, eta, dt_out);
+    if (rc != ABACUS_NF_OK) return rc;
     if (hipGetDevice(dev) != hipSuccess) return hip_fail(hipErrorUnknown);
     if (*dev != h->device) return ABACUS_NF_ESTATE;
     return ABACUS_NF_OK;
@@ -612,6 +619,10 @@ int abacus_nf_timestep(abacus_nf_cells h, const float *vel, const float *acc, do
 namespace anf {
 
 int handle_boxes(abacus_nf_cells h) { return h ? h->n_boxes : 0; }
+
+int timestep_arguments(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out) {
+    return timestep_args(h, vel, acc, eta, dt_out);
+}
 
 int timestep_with_buffers(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
                           double *partials, size_t partial_doubles, unsigned long long *dmin, int dmin_count,

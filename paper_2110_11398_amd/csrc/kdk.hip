@@ -210,8 +210,10 @@ __global__ __launch_bounds__(256) void k_ts_units(TsArgs a) {
             const float t = __shfl(v[b][d], sl);
             r[d] = below ? t : carry_ref[d];
         }
+        // the cell of the next batch's first slot (every lane takes part in the cross-lane read)
+        const int first_next = __shfl(key[b + 1 < kTsBatches ? b + 1 : b], 0);
         int nxt = __shfl_down(k, 1);
-        if (lane == nb - 1) nxt = (b0 + 64 < s1) ? __shfl(key[b + 1 < kTsBatches ? b + 1 : b], 0) : ~k;
+        if (lane == nb - 1) nxt = (b0 + 64 < s1) ? first_next : ~k;   // the unit's end closes a segment
         const bool end = live && k != nxt;
         const unsigned long long endmask = __ballot(end);
         double x[kTsVals] = {0.0, 0.0, 0.0, 0.0, 0.0};

@@ -256,5 +256,7 @@ int timestep_with_buffers(abacus_nf_cells h, const float *vel, const float *acc,
                           double *partials, size_t partial_doubles, unsigned long long *dmin, int dmin_count,
                           void *hip_stream);
 int handle_boxes(abacus_nf_cells h);   // boxes of a handle (0 for NULL)
+// The argument and state checks of abacus_nf_timestep alone (no HIP call).
+int timestep_arguments(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out);
 
 }  // namespace anf
