@@ -51,6 +51,8 @@ extern "C" {
 #define ABACUS_NF_ECAPACITY -4  /* a device-side list outgrew its allocation      */
 #define ABACUS_NF_ENONFINITE -5 /* a position was NaN or infinite                 */
 #define ABACUS_NF_ESTATE -6     /* handle used in the wrong state                 */
+#define ABACUS_NF_ELIMIT -7     /* batch larger than the fixed scratch of an entry
+                                   point that allocates nothing                   */
 
 /* Softening law (Sec. 2.5, Sec. 5.2). */
 typedef enum {
@@ -246,6 +248,22 @@ int abacus_nf_drift(abacus_nf_cells cells, const double *dt, const float *vel, f
  */
 int abacus_nf_timestep(abacus_nf_cells cells, const float *vel, const float *acc, double eta, double *dt_out,
                        void *hip_stream);
+
+/*
+ * abacus_nf_timestep_noalloc -- abacus_nf_timestep for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same criterion, kernels, arguments and
+ * result, with its unit partials and per-box minima in a fixed scratch array
+ * of the library (8 MiB of device memory per device it runs on, held until the
+ * process ends) instead of buffers of the handle.  It calls no allocating
+ * routine.  Limits: n_total <= 2^24 particles and n_boxes <= 4096; larger
+ * batches return ABACUS_NF_ELIMIT before any HIP call.  Every call on a device
+ * shares that device's scratch array (each call refills what it reads), so
+ * calls that overlap on one device -- two streams, two host threads -- race;
+ * the caller must serialise them.  Blocks on the stream like abacus_nf_timestep.
+ */
+int abacus_nf_timestep_noalloc(abacus_nf_cells cells, const float *vel, const float *acc, double eta,
+                               double *dt_out, void *hip_stream);
 
 /*
  * abacus_nf_kdk_step -- one leapfrog step of size dt per box, near field only:

@@ -19,7 +19,7 @@ SPLINE, PLUMMER = 0, 1
 SUM_FP32, SUM_COMP32, SUM_FP64 = 0, 1, 2
 ARRAY_PERM, ARRAY_CELL_START, ARRAY_SPOS, ARRAY_CELL_KEY, ARRAY_CELL_AMAX2 = 0, 1, 2, 3, 4
 
-OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, ENONFINITE, ESTATE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 
 
 class BoxDesc(ctypes.Structure):
@@ -72,6 +72,7 @@ def library():
         "abacus_nf_reorder": [vp, ctypes.POINTER(vp), i32, vp, vp],
         "abacus_nf_drift": [vp, ctypes.POINTER(d), vp, vp, vp],
         "abacus_nf_timestep": [vp, vp, vp, d, ctypes.POINTER(d), vp],
+        "abacus_nf_timestep_noalloc": [vp, vp, vp, d, ctypes.POINTER(d), vp],
         "abacus_nf_kdk_step": [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.c_int, ctypes.POINTER(d),
                                ctypes.c_int, vp, vp, vp, vp],
         "abacus_nf_sync": [vp],
@@ -269,6 +270,15 @@ class Cells:
         rc = library().abacus_nf_timestep(self._h, self._vec3(vel, "vel"), a, float(eta), out,
                                           ctypes.c_void_p(_stream_handle(stream)))
         _check(rc, "abacus_nf_timestep")
+        return list(out)
+
+    def timestep_noalloc(self, vel, acc=None, eta: float = 0.25, stream=None) -> List[float]:
+        """abacus_nf_timestep_noalloc: the same criterion with the library's fixed scratch (no allocation)."""
+        out = (ctypes.c_double * len(self.boxes))()
+        a = self._vec3(acc, "acc") if acc is not None else ctypes.c_void_p(None)
+        rc = library().abacus_nf_timestep_noalloc(self._h, self._vec3(vel, "vel"), a, float(eta), out,
+                                                  ctypes.c_void_p(_stream_handle(stream)))
+        _check(rc, "abacus_nf_timestep_noalloc")
         return list(out)
 
     def reorder(self, arrays, ids=None, stream=None):

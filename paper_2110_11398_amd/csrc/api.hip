@@ -240,6 +240,7 @@ const char *abacus_nf_strerror(int code) {
         case ABACUS_NF_ECAPACITY: return "device work list outgrew its capacity";
         case ABACUS_NF_ENONFINITE: return "non-finite particle position";
         case ABACUS_NF_ESTATE: return "handle used in the wrong state";
+        case ABACUS_NF_ELIMIT: return "batch exceeds the fixed scratch of an entry point that allocates nothing";
         default: return "unknown error code";
     }
 }

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_strerror_and_version(lib):
     import paper_2110_11398_amd as nf
     assert nf.version() >= 10000
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert nf.strerror(code) and "unknown" not in nf.strerror(code)
     assert "unknown" in nf.strerror(-99)
 
