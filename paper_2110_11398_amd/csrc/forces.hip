@@ -252,6 +252,15 @@ __global__ void k_wl_classes(WorkState *ws, int64_t item_capacity, const int64_t
     // reported by abacus_nf_sync and the output is left unwritten
     ws->n_items = over ? 0 : (int32_t)run;
     for (int q = 0; q < kQueues; q++) ws->cursor[q] = 0;
+    // slot j of queue x holds item ((j / kQueueBlock) * kQueues + x) * kQueueBlock + j % kQueueBlock, increasing
+    // in j: the first slot of each queue at or past the first light item
+    const int64_t L0 = ws->class_base[kLightClass];
+    const int64_t B = L0 / kQueueBlock, o = L0 % kQueueBlock;
+    for (int x = 0; x < kQueues; x++) {
+        const int64_t bq = B > x ? (B - x + kQueues - 1) / kQueues : 0;   // first block of queue x at or past B
+        const int64_t slot = bq * kQueueBlock + (bq * kQueues + x == B ? o : 0);
+        ws->light_slot[x] = (int32_t)(slot < INT_MAX ? slot : INT_MAX);
+    }
     ws->overflow = over ? 1 : 0;
     if (over) atomicCAS(err, 0, ABACUS_NF_ECAPACITY);
 }
@@ -457,20 +466,31 @@ void k_forces(KArgs a) {
     const int home = blockIdx.x % kQueues;
     int queue = 0;  // queues tried so far (own queue first, then the others in turn)
 
+    int jnext = 0, jleft = 0;   // slots of the current queue claimed and not yet taken: [jnext, jnext + jleft)
     for (;;) {
-        // next item: the j-th item of queue x lives in block x + kQueues*(j / kQueueBlock)
+        // next item: slot j of queue x holds item x + kQueues*(j / kQueueBlock) (block) of the list; one atomic
+        // claims one slot, or kLightClaim slots once the queue has reached its light items
         int k = n_items;
         while (queue < kQueues) {
             const int x = (home + queue) % kQueues;
-            int j = 0;
-            if (lane == 0) j = atomicAdd(&a.ws->cursor[x], 1);
-            j = sgpr(__shfl(j, 0));
+            if (jleft == 0) {
+                const int want = jnext >= a.ws->light_slot[x] ? kLightClaim : 1;
+                int j = 0;
+                if (lane == 0) j = atomicAdd(&a.ws->cursor[x], want);
+                jnext = sgpr(__shfl(j, 0));
+                jleft = want;
+            }
+            const int j = jnext;
+            jnext++;
+            jleft--;
             const int64_t idx = ((int64_t)(j / kQueueBlock) * kQueues + x) * kQueueBlock + j % kQueueBlock;
             if (idx < n_items) {
                 k = (int)idx;
                 break;
             }
-            queue++;  // queue x is drained (its later indices only grow)
+            queue++;  // queue x is drained (its later slots only grow)
+            jnext = 0;
+            jleft = 0;
         }
         if (k >= n_items) break;
         const Item it = a.items[k];

@@ -44,6 +44,11 @@ constexpr int kNumClasses = 64;
 // cells then share one XCD's L2.
 constexpr int kQueues = 8;
 constexpr int kQueueBlock = 32;
+// Items of the light cost classes (an item of class >= kLightClass costs under ~1024 source iterations x sinks
+// per lane) are claimed kLightClaim queue slots per atomic: sparse regions hold millions of such items, and one
+// atomic per item on the queue cursors would bound the kernel.
+constexpr int kLightClass = 44;
+constexpr int kLightClaim = 8;
 
 // Device-side state of the work list of one forces call.
 struct WorkState {
@@ -58,6 +63,7 @@ struct WorkState {
     int32_t class_count[kNumClasses];
     int32_t class_fill[kNumClasses];
     int32_t class_base[kNumClasses];
+    int32_t light_slot[kQueues];       // first slot of each queue that holds a light item
 };
 
 // Sink tiles of one cell.  The n sinks form g = ceil(n / S) groups of S (one
