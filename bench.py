@@ -39,12 +39,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+HEADER_MARK = b"// (The definitions above are all the force kernel takes from this header.)"
+
+
 def kernel_source_digest() -> str:
-    """Digest of the force kernel's sources: its file and the shared header that holds the tile geometry (a
-    counter summary is valid only for these sources)."""
+    """Digest of the force kernel's sources: its file and the part of the shared header it uses (the work
+    items, queues and tile geometry, up to the marker line), so a counter summary is valid only for these
+    sources."""
     h = hashlib.sha256()
-    for f in ("forces.hip", "nf_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2110_11398_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2110_11398_amd", "csrc")
+    h.update(open(os.path.join(csrc, "forces.hip"), "rb").read())
+    header = open(os.path.join(csrc, "nf_internal.h"), "rb").read()
+    h.update(header.split(HEADER_MARK)[0])
     return h.hexdigest()[:16]
 
 

@@ -40,7 +40,7 @@ struct abacus_nf_cells_s {
     // leapfrog: per-box step sizes (kick, drift), timestep partials and per-box minima
     int scap_boxes = -1;
     double *d_dt = nullptr;                 // [2][n_boxes]
-    unsigned long long *ts_min = nullptr;   // [n_boxes]
+    unsigned long long *ts_min = nullptr;   // timestep_min_words(n_boxes): per-box slots, then final minima
     size_t ts_cap = 0;
     double *ts_partials = nullptr;
     // merge scratch (n_total x 12 bytes)
@@ -516,7 +516,7 @@ static int ensure_step_buffers(abacus_nf_cells_s *h, bool timestep) {
         dfree(h->d_dt);
         dfree(h->ts_min);
         h->scap_boxes = -1;
-        if (!dalloc(h->d_dt, 2 * (size_t)h->n_boxes) || !dalloc(h->ts_min, (size_t)h->n_boxes)) {
+        if (!dalloc(h->d_dt, 2 * (size_t)h->n_boxes) || !dalloc(h->ts_min, timestep_min_words(h->n_boxes))) {
             free_step_buffers(h);
             return ABACUS_NF_ENOMEM;
         }
@@ -596,7 +596,8 @@ static int timestep_run(abacus_nf_cells h, const float *vel, const float *acc, d
                                    h->n_total, partials, dmin, st);
     if (e != hipSuccess) return hip_fail(e);
     static_assert(sizeof(double) == sizeof(unsigned long long), "bit copies of doubles");
-    if (hipMemcpyAsync(dt_out, dmin, (size_t)h->n_boxes * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    if (hipMemcpyAsync(dt_out, dmin + timestep_min_offset(h->n_boxes), (size_t)h->n_boxes * sizeof(double),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return hip_fail(hipErrorUnknown);
     for (int b = 0; b < h->n_boxes; b++) {
@@ -626,12 +627,13 @@ int timestep_arguments(abacus_nf_cells h, const float *vel, const float *acc, do
 }
 
 int timestep_with_buffers(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
-                          double *partials, size_t partial_doubles, unsigned long long *dmin, int dmin_count,
+                          double *partials, size_t partial_doubles, unsigned long long *dmin, size_t dmin_words,
                           void *hip_stream) {
     int dev = 0;
     int rc = timestep_checks(h, vel, acc, eta, dt_out, &dev);
     if (rc != ABACUS_NF_OK) return rc;
-    if (!partials || !dmin || partial_doubles < timestep_partial_doubles(h->n_total) || dmin_count < h->n_boxes)
+    if (!partials || !dmin || partial_doubles < timestep_partial_doubles(h->n_total) ||
+        dmin_words < timestep_min_words(h->n_boxes))
         return ABACUS_NF_EINVAL;
     return timestep_run(h, vel, acc, eta, dt_out, partials, dmin, (hipStream_t)hip_stream);
 }

@@ -42,6 +42,10 @@ constexpr int kDtChunk = 24;
 constexpr int kTsUnit = 256;                 // slots per wave of the timestep pass
 constexpr int kTsBatches = kTsUnit / 64;
 constexpr int kTsVals = 5;   // S1x, S1y, S1z, S2, A
+// Per-box minima are kept in kTsSlots slots per box (a wave or boundary folds into slot index mod kTsSlots),
+// so that the atomic minima of thousands of waves do not all meet on one address; a last kernel takes the
+// minimum over the slots of each box.
+constexpr int kTsSlots = 64;
 
 struct DtChunk {
     double v[kDtChunk];
@@ -124,7 +128,7 @@ struct TsArgs {
     int n_boxes;
     int64_t n;
     double *partials;             // [2 per unit][kTsVals]: head, tail
-    unsigned long long *dmin;     // [n_boxes] bits of the smallest sigma / |a|max
+    unsigned long long *dmin;     // [n_boxes][kTsSlots] bits of the smallest sigma / |a|max, then [n_boxes] final
 };
 
 // |x|^2 with every product and sum rounded on its own, in a fixed order (the same value the caller gets
@@ -144,9 +148,14 @@ __device__ inline double cell_ratio(const double *t, int n, double A) {
     return sqrt(s2) / sqrt(A);
 }
 
-__device__ inline void fold_min(unsigned long long *dmin, int box, double r) {
-    atomicMin(dmin + box, (unsigned long long)__double_as_longlong(r));
+__device__ inline void fold_min(unsigned long long *dmin, int box, int64_t slot, double r) {
+    atomicMin(dmin + (int64_t)box * kTsSlots + slot % kTsSlots, (unsigned long long)__double_as_longlong(r));
 }
+
+// Three consecutive floats, read with one 12-byte load.
+struct F3 {
+    float x, y, z;
+};
 
 // One wave per unit of kTsUnit sorted slots.  Every load of the unit is issued before the first sum: keys
 // and permutation entries (coalesced), then the velocities (and accelerations) gathered through the
@@ -170,11 +179,17 @@ __global__ __launch_bounds__(256) void k_ts_units(TsArgs a) {
         const int64_t s = s0 + 64 * b + lane;
         key[b] = s < s1 ? a.keys[s] : -2;
         const int64_t p = s < s1 ? a.perm[s] : 0;
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            v[b][d] = s < s1 ? a.vel[3 * p + d] : 0.f;
-            g[b][d] = (!FUSED && s < s1) ? a.acc[3 * p + d] : 0.f;
+        F3 tv = {0.f, 0.f, 0.f}, tg = {0.f, 0.f, 0.f};
+        if (s < s1) {
+            tv = reinterpret_cast<const F3 *>(a.vel)[p];
+            if (!FUSED) tg = reinterpret_cast<const F3 *>(a.acc)[p];
         }
+        v[b][0] = tv.x;
+        v[b][1] = tv.y;
+        v[b][2] = tv.z;
+        g[b][0] = tg.x;
+        g[b][1] = tg.y;
+        g[b][2] = tg.z;
     }
     const int unit_prev = s0 > 0 ? a.keys[s0 - 1] : -1;
     const int after = s1 < a.n ? a.keys[s1] : -1;
@@ -260,7 +275,7 @@ __global__ __launch_bounds__(256) void k_ts_units(TsArgs a) {
                 if (rr >= 0.0) {
                     const int bx = a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, k) : 0;
                     if (bx != lane_box) {
-                        if (lane_box >= 0) fold_min(a.dmin, lane_box, lane_min);
+                        if (lane_box >= 0) fold_min(a.dmin, lane_box, u, lane_min);
                         lane_box = bx;
                         lane_min = rr;
                     } else {
@@ -292,7 +307,19 @@ __global__ __launch_bounds__(256) void k_ts_units(TsArgs a) {
             carry_key = -1;
         }
     }
-    if (lane_box >= 0) fold_min(a.dmin, lane_box, lane_min);
+    // the wave's minima, one atomic per box present in the wave (normally one box)
+    for (;;) {
+        const unsigned long long pending = __ballot(lane_box >= 0);
+        if (!pending) break;
+        const int bx = __shfl(lane_box, __builtin_ctzll(pending));
+        double m = lane_box == bx ? lane_min : __longlong_as_double(0x7FF0000000000000ll);
+        for (int off = 32; off > 0; off >>= 1) {
+            const double y = __shfl_xor(m, off);
+            m = y < m ? y : m;
+        }
+        if (lane == 0) fold_min(a.dmin, bx, u, m);
+        if (lane_box == bx) lane_box = -1;
+    }
 }
 
 // Cells that cross unit boundaries, one wave per boundary: at the first boundary a cell crosses, the
@@ -331,7 +358,19 @@ __global__ __launch_bounds__(256) void k_ts_combine(TsArgs a) {
     for (int q = 0; q < 4; q++) s[q] = tail[q] + t[q];
     const double A = FUSED ? __longlong_as_double((long long)a.amax[c]) : (tail[4] > t[4] ? tail[4] : t[4]);
     const double r = cell_ratio(s, a.cs[c + 1] - a.cs[c], A);
-    if (r >= 0.0) fold_min(a.dmin, a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, c) : 0, r);
+    if (r >= 0.0) fold_min(a.dmin, a.n_boxes > 1 ? box_of_cell(a.boxes, a.n_boxes, c) : 0, u, r);
+}
+
+// Minimum over the slots of each box, into the final words after the slots.
+__global__ void k_ts_final(unsigned long long *dmin, int n_boxes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_boxes) return;
+    unsigned long long m = dmin[(int64_t)b * kTsSlots];
+    for (int q = 1; q < kTsSlots; q++) {
+        const unsigned long long y = dmin[(int64_t)b * kTsSlots + q];
+        m = y < m ? y : m;
+    }
+    dmin[(int64_t)n_boxes * kTsSlots + b] = m;
 }
 
 int grid_of(int64_t n, int threads, int device, int per_cu) {
@@ -410,10 +449,14 @@ hipError_t launch_timestep(const float *vel, const float *acc, const unsigned lo
                            const int32_t *perm, const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n,
                            double *partials, unsigned long long *dmin, hipStream_t st) {
     const unsigned long long inf_bits = 0x7FF0000000000000ull;
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n_boxes + 255) / 256)), dim3(256), 0, st, dmin,
-                       (int64_t)n_boxes, inf_bits);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n <= 0) return e;
+    const int64_t nslots = (int64_t)n_boxes * kTsSlots;
+    hipError_t e = launch_fill_u64(dmin, nslots, inf_bits, st);
+    if (e != hipSuccess) return e;
+    auto final_min = [&]() {
+        hipLaunchKernelGGL(k_ts_final, dim3((unsigned)((n_boxes + 63) / 64)), dim3(64), 0, st, dmin, n_boxes);
+        return hipGetLastError();
+    };
+    if (n <= 0) return final_min();
     TsArgs a;
     a.vel = vel;
     a.acc = acc;
@@ -430,10 +473,17 @@ hipError_t launch_timestep(const float *vel, const float *acc, const unsigned lo
     const bool fused = acc == nullptr;
     hipLaunchKernelGGL(fused ? k_ts_units<true> : k_ts_units<false>, dim3((unsigned)((n_units + 3) / 4)), dim3(256),
                        0, st, a);
-    if ((e = hipGetLastError()) != hipSuccess || n_units < 2) return e;
-    hipLaunchKernelGGL(fused ? k_ts_combine<true> : k_ts_combine<false>, dim3((unsigned)((n_units - 1 + 3) / 4)),
-                       dim3(256), 0, st, a);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n_units >= 2) {
+        hipLaunchKernelGGL(fused ? k_ts_combine<true> : k_ts_combine<false>,
+                           dim3((unsigned)((n_units - 1 + 3) / 4)), dim3(256), 0, st, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return final_min();
 }
+
+size_t timestep_min_words(int n_boxes) { return (size_t)n_boxes * (kTsSlots + 1); }
+
+size_t timestep_min_offset(int n_boxes) { return (size_t)n_boxes * kTsSlots; }
 
 }  // namespace anf

@@ -164,6 +164,8 @@ __device__ inline int box_of_cell(const BoxDev *boxes, int n_boxes, int32_t c) {
     return lo;
 }
 
+// (The definitions above are all the force kernel takes from this header.)
+
 // Error reporting: the first device error since the last abacus_nf_sync.
 int *device_error_word(int device);   // host accessor (allocates on first use)
 
@@ -254,12 +256,16 @@ hipError_t launch_timestep(const float *vel, const float *acc, const unsigned lo
                            const int32_t *perm, const int32_t *cs, const BoxDev *boxes, int n_boxes, int64_t n,
                            double *partials, unsigned long long *dmin, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
+// Words of the per-box minima buffer of the timestep criterion (slots per box, then one final word per
+// box), and where the final words start.
+size_t timestep_min_words(int n_boxes);
+size_t timestep_min_offset(int n_boxes);
 
 // The step-size criterion of a handle with buffers the caller provides (api.hip): partials of at least
-// timestep_partial_doubles(n_total) doubles and per-box minima of at least n_boxes entries.  The argument
-// checks of abacus_nf_timestep come first; EINVAL when a buffer is missing or too small.
+// timestep_partial_doubles(n_total) doubles and per-box minima of at least timestep_min_words(n_boxes)
+// words.  The argument checks of abacus_nf_timestep come first; EINVAL when a buffer is missing or too small.
 int timestep_with_buffers(abacus_nf_cells h, const float *vel, const float *acc, double eta, double *dt_out,
-                          double *partials, size_t partial_doubles, unsigned long long *dmin, int dmin_count,
+                          double *partials, size_t partial_doubles, unsigned long long *dmin, size_t dmin_words,
                           void *hip_stream);
 int handle_boxes(abacus_nf_cells h);   // boxes of a handle (0 for NULL)
 // The argument and state checks of abacus_nf_timestep alone (no HIP call).

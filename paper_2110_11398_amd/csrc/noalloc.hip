@@ -13,7 +13,8 @@
 
 namespace {
 
-// Layout of the scratch array: per-box minima first, then the unit partials.
+// Layout of the scratch array: the per-box minima (slots and final words for up to kNoAllocMaxBoxes boxes)
+// first, then the unit partials.
 constexpr int kNoAllocMaxBoxes = 4096;
 constexpr int64_t kNoAllocMaxParticles = int64_t(1) << 24;
 constexpr size_t kNoAllocDoubles = size_t(1) << 20;   // 8 MiB per device
@@ -48,8 +49,9 @@ extern "C" int abacus_nf_timestep_noalloc(abacus_nf_cells h, const float *vel, c
     if (rc != ABACUS_NF_OK) return rc;
     int64_t n = 0, n_cells = 0;
     if ((rc = abacus_nf_cells_size(h, &n, &n_cells)) != ABACUS_NF_OK) return rc;
+    const size_t min_words = anf::timestep_min_words(kNoAllocMaxBoxes);
     if (n > kNoAllocMaxParticles || anf::handle_boxes(h) > kNoAllocMaxBoxes ||
-        anf::timestep_partial_doubles(n) > kNoAllocDoubles - kNoAllocMaxBoxes)
+        anf::timestep_partial_doubles(n) > kNoAllocDoubles - min_words)
         return ABACUS_NF_ELIMIT;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -61,7 +63,7 @@ extern "C" int abacus_nf_timestep_noalloc(abacus_nf_cells h, const float *vel, c
     // the minima are refilled with +inf by the criterion itself, and every partial it reads is written by the
     // same call, so nothing left by an earlier call is read
     unsigned long long *dmin = reinterpret_cast<unsigned long long *>(base);
-    double *partials = base + kNoAllocMaxBoxes;
-    return anf::timestep_with_buffers(h, vel, acc, eta, dt_out, partials, kNoAllocDoubles - kNoAllocMaxBoxes, dmin,
-                                      kNoAllocMaxBoxes, hip_stream);
+    double *partials = base + min_words;
+    return anf::timestep_with_buffers(h, vel, acc, eta, dt_out, partials, kNoAllocDoubles - min_words, dmin,
+                                      min_words, hip_stream);
 }
