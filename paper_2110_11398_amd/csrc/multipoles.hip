@@ -10,19 +10,26 @@
 //
 // (u, v, w) = position relative to the cell centre in cell widths.
 //
+// The sums run on the matrix cores.  Every component is a product of a "row"
+// monomial and a "column" monomial, R_r C_c, taken from two sets of 16
+// monomials each (a cover of the order, below), so the moments of a cell are
+// entries of the 16 x 16 matrix sum_j R(j) C(j)^T -- a product with the
+// particles as the inner index, four particles per v_mfma_f64_16x16x4f64.
+// Orders 9 and 10 take two such tiles.  Each lane writes its particle's
+// monomials to a row of LDS once per batch; a matrix step then reads one row
+// and one column value per lane and tile.
+//
 // Work is cut by particle: a work unit is kMpUnit consecutive slots of the
 // sorted layout, whatever cells they hold, so every unit carries the same work
 // (a halo core spans several units, a sparse region packs many cells into one).
-// One wave walks its unit in batches of B slots: each lane writes one
-// particle's powers to LDS as x^a y^b (a + b <= p) and w^k, then every lane
-// adds the particles of the batch, in slot order, to the components it owns:
-// a 2 x 2 block {x^a y^b, x^a' y^b'} x {w^k, w^k+1} (a + b = a' + b'), four
-// LDS reads for four FMAs.  At each cell
-// boundary the wave writes the cell's moments: directly when the whole cell
-// lies in the unit, else as the unit's head or tail partial, which k_mp_combine
-// adds in a fixed order.  Empty cells are written as zeros by the unit holding
-// the next occupied cell (or the last unit, for trailing ones).  FP64
-// throughout and fixed orders, so the result does not depend on scheduling.
+// At each cell boundary the wave writes the cell's moments: directly when the
+// whole cell lies in the unit, else as the unit's head or tail partial, which
+// k_mp_combine adds in a fixed order.  Empty cells are written as zeros by the
+// unit holding the next occupied cell (or the last unit, for trailing ones).
+// FP64 throughout and fixed orders, so the result does not depend on
+// scheduling.
+#include <utility>
+
 #include "nf_internal.h"
 
 namespace anf {
@@ -31,9 +38,7 @@ namespace {
 
 constexpr int kMaxOrder = 10;
 constexpr int kMpUnit = 1024;   // slots per work unit
-// slots per LDS power table: 32, or 16 when cells hold fewer than 16 particles on average (smaller tables,
-// more waves in flight for the per-cell work; measured on the late-time workload: 13.6 -> 11.9 ms)
-constexpr int kMpBatchWide = 32, kMpBatchNarrow = 16;
+constexpr int kMxBatch = 32;   // slots per batch (rows of the LDS monomial table)
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -41,43 +46,154 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Column of x^a y^b in a power-table row: rows a = 0..P, each b = 0..P-a.
-__host__ __device__ constexpr int xy_index(int P1, int a, int b) { return a * P1 - a * (a - 1) / 2 + b; }
-
 // Position of component (a, b, k) in the degree / a-descending / b-descending order.
 __host__ __device__ constexpr int comp_index(int a, int b, int k) {
     const int n = a + b + k;
     return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
 }
 
-// The components are covered by 2 x 2 blocks {x^a y^b, x^a' y^b'} x {w^k, w^k'} with a + b = a' + b' = s
-// and k' = k + 1, so a lane reads at most four powers per particle for up to four products (instead of
-// two reads per product).  Blocks are numbered by s, then by the pair of (a, b) entries (a descending),
-// then by the pair of k; a pair may hold a single entry at the end of its range.
-__host__ __device__ constexpr int mp_blocks(int P) {
-    int n = 0;
-    for (int s = 0; s <= P; s++) n += ((s + 2) / 2) * ((P - s + 2) / 2);
-    return n;
+__host__ __device__ constexpr int n_components(int P) { return (P + 1) * (P + 2) * (P + 3) / 6; }
+
+// ---------------------------------------------------------------- covers
+//
+// A cover of order p: tiles of 16 row and 16 column monomials x^a y^b w^k
+// such that every component a + b + k <= p is the product of a row and a
+// column monomial of one tile (products of higher degree are computed and
+// dropped).  Orders up to 7 and order 9 use the digit split
+//     x^A y^B w^K = (x^a y^b) (x^4i y^4j w^K),  A = 4i + a, B = 4j + b,  a, b < 4,
+// rows x^a y^b and columns x^4i y^4j w^K (4i + 4j + K <= p), cut into tiles of
+// 16 columns (the same rows in each).  That split needs 22 columns at order 8
+// and 34 at order 10; the covers used there (one tile of 16 x 16 for the 165
+// components of order 8, two for the 286 of order 10) were found by a
+// randomized search over pairs of monomial sets.  static_asserts below check
+// that every cover reaches every component.
+struct MxMono {
+    int a, b, k;   // exponents of u, v, w; a < 0 marks an unused column (value 0)
+};
+constexpr int kMxMaxTiles = 2;
+struct MxCover {
+    int nt;
+    MxMono row[kMxMaxTiles][16];
+    MxMono col[kMxMaxTiles][16];
+};
+
+constexpr MxMono kMxRow8[16] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 3}, {0, 0, 4}, {0, 1, 0}, {0, 1, 2}, {0, 2, 1}, {0, 3, 0},
+                                {1, 0, 2}, {1, 1, 1}, {1, 2, 0}, {2, 0, 0}, {2, 0, 1}, {2, 1, 0}, {3, 0, 0}, {4, 0, 0}};
+constexpr MxMono kMxCol8[16] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 4}, {0, 0, 5}, {0, 2, 0}, {0, 3, 0}, {0, 4, 0}, {0, 5, 0},
+                                {1, 0, 0}, {1, 0, 1}, {1, 1, 3}, {1, 2, 1}, {2, 0, 1}, {2, 2, 1}, {4, 0, 0}, {5, 0, 0}};
+constexpr MxMono kMxRow10[2][16] = {
+    {{0, 0, 2}, {0, 1, 1}, {0, 1, 2}, {0, 2, 0}, {0, 2, 1}, {0, 3, 0}, {1, 0, 1}, {1, 0, 2},
+     {1, 1, 0}, {1, 1, 1}, {1, 2, 0}, {2, 0, 0}, {2, 0, 1}, {2, 1, 0}, {3, 0, 0}, {3, 0, 2}},
+    {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 0}, {0, 1, 1}, {0, 1, 2}, {0, 4, 0}, {0, 5, 3},
+     {1, 0, 0}, {1, 0, 1}, {1, 1, 0}, {1, 1, 1}, {1, 2, 4}, {2, 0, 0}, {2, 2, 0}, {6, 0, 0}}};
+constexpr MxMono kMxCol10[2][16] = {
+    {{0, 0, 3}, {0, 0, 5}, {0, 3, 0}, {0, 4, 0}, {0, 5, 2}, {1, 1, 0}, {1, 1, 5}, {1, 3, 2},
+     {2, 3, 0}, {2, 5, 0}, {3, 0, 0}, {4, 0, 3}, {4, 3, 0}, {5, 0, 0}, {5, 0, 2}, {6, 1, 0}},
+    {{0, 0, 0}, {0, 0, 2}, {0, 0, 6}, {0, 0, 8}, {0, 2, 0}, {0, 2, 6}, {0, 3, 3}, {0, 6, 0},
+     {0, 8, 0}, {2, 0, 0}, {2, 0, 4}, {2, 0, 6}, {2, 2, 3}, {3, 0, 3}, {3, 2, 1}, {8, 0, 0}}};
+
+constexpr MxCover mx_cover(int P) {
+    MxCover v{};
+    if (P == 8) {
+        v.nt = 1;
+        for (int i = 0; i < 16; i++) {
+            v.row[0][i] = kMxRow8[i];
+            v.col[0][i] = kMxCol8[i];
+        }
+        return v;
+    }
+    if (P == 10) {
+        v.nt = 2;
+        for (int t = 0; t < 2; t++)
+            for (int i = 0; i < 16; i++) {
+                v.row[t][i] = kMxRow10[t][i];
+                v.col[t][i] = kMxCol10[t][i];
+            }
+        return v;
+    }
+    // digit split
+    int nc = 0;
+    for (int t = 0; t < kMxMaxTiles; t++)
+        for (int i = 0; i < 16; i++) v.col[t][i] = MxMono{-1, 0, 0};
+    for (int i = 0; 4 * i <= P; i++)
+        for (int j = 0; 4 * i + 4 * j <= P; j++)
+            for (int k = 0; 4 * i + 4 * j + k <= P; k++, nc++) v.col[nc / 16][nc % 16] = MxMono{4 * i, 4 * j, k};
+    v.nt = (nc + 15) / 16;
+    for (int t = 0; t < v.nt; t++)
+        for (int r = 0; r < 16; r++) v.row[t][r] = MxMono{r & 3, r >> 2, 0};
+    return v;
 }
 
-// Block idx: its two (a, b) entries (the second may be absent: b2 < 0) and two k (k2 < 0 if absent).
-__device__ inline void mp_block(int P, int idx, int &a1, int &b1, int &a2, int &b2, int &k1, int &k2) {
-    for (int s = 0; s <= P; s++) {
-        const int nx = (s + 2) / 2, nk = (P - s + 2) / 2;
-        if (idx < nx * nk) {
-            const int j = idx / nk, t = idx % nk;
-            a1 = s - 2 * j;
-            b1 = 2 * j;
-            a2 = 2 * j + 1 <= s ? s - 2 * j - 1 : 0;
-            b2 = 2 * j + 1 <= s ? 2 * j + 1 : -1;
-            k1 = 2 * t;
-            k2 = 2 * t + 1 <= P - s ? 2 * t + 1 : -1;
-            return;
-        }
-        idx -= nx * nk;
+// Component of every (tile, row, column) entry: the first entry in (tile, row, column) order whose product is
+// the component stands for it; every other entry is -1.
+struct MxMap {
+    short comp[kMaxOrder + 1][kMxMaxTiles][16][16];
+    bool complete[kMaxOrder + 1];
+};
+
+constexpr MxMap mx_map() {
+    MxMap m{};
+    for (int P = 0; P <= kMaxOrder; P++) {
+        const MxCover cv = mx_cover(P);
+        bool seen[n_components(kMaxOrder)] = {};
+        for (int t = 0; t < kMxMaxTiles; t++)
+            for (int r = 0; r < 16; r++)
+                for (int c = 0; c < 16; c++) {
+                    m.comp[P][t][r][c] = -1;
+                    if (t >= cv.nt || cv.col[t][c].a < 0) continue;
+                    const int A = cv.row[t][r].a + cv.col[t][c].a, B = cv.row[t][r].b + cv.col[t][c].b,
+                              K = cv.row[t][r].k + cv.col[t][c].k;
+                    if (A + B + K > P) continue;
+                    const int ci = comp_index(A, B, K);
+                    if (seen[ci]) continue;
+                    seen[ci] = true;
+                    m.comp[P][t][r][c] = (short)ci;
+                }
+        bool all = true;
+        for (int i = 0; i < n_components(P); i++) all = all && seen[i];
+        m.complete[P] = all;
     }
-    a1 = b1 = a2 = k1 = 0;
-    b2 = k2 = -1;
+    return m;
+}
+
+constexpr MxMap kMxMapHost = mx_map();
+static_assert(kMxMapHost.complete[0] && kMxMapHost.complete[1] && kMxMapHost.complete[2] &&
+                  kMxMapHost.complete[3] && kMxMapHost.complete[4] && kMxMapHost.complete[5] &&
+                  kMxMapHost.complete[6] && kMxMapHost.complete[7] && kMxMapHost.complete[8] &&
+                  kMxMapHost.complete[9] && kMxMapHost.complete[10],
+              "a multipole cover misses a component");
+static_assert(mx_cover(8).nt == 1 && mx_cover(9).nt == 2 && mx_cover(10).nt == 2, "tiles per order");
+
+__constant__ MxMap kMxMap = mx_map();
+
+// Entry idx of a particle's LDS row (idx a compile-time constant): entries 32 t .. 32 t + 15 hold the row
+// monomials of tile t, 32 t + 16 .. 32 t + 31 its column monomials.  Unused columns, and monomials of a degree
+// beyond p along one axis (which reach no component), are zeros.
+template <int P, int idx>
+__device__ inline double mx_entry(const double (&xp)[P + 1], const double (&yp)[P + 1], const double (&zp)[P + 1]) {
+    constexpr MxCover cv = mx_cover(P);
+    constexpr MxMono m = (idx & 31) < 16 ? cv.row[idx >> 5][idx & 15] : cv.col[idx >> 5][idx & 15];
+    if constexpr (m.a < 0 || m.a > P || m.b > P || m.k > P) {
+        return 0.0;
+    } else {
+        return xp[m.a] * yp[m.b] * zp[m.k];
+    }
+}
+
+template <int P, int... is>
+__device__ inline void mx_write_row(double *row, const double (&xp)[P + 1], const double (&yp)[P + 1],
+                                    const double (&zp)[P + 1], std::integer_sequence<int, is...>) {
+    ((row[is] = mx_entry<P, is>(xp, yp, zp)), ...);
+}
+
+typedef double mx_acc __attribute__((ext_vector_type(4)));
+
+// A wave-uniform double held in scalar registers.
+__device__ inline double uniform_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 struct MpArgs {
@@ -109,36 +225,23 @@ __global__ void k_zero_f64(double *p, int64_t n) {
         p[i] = 0.0;
 }
 
-template <int P, int kMpBatch>
+template <int P, int B>
 __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
     constexpr int P1 = P + 1;
-    constexpr int NXY = P1 * (P1 + 1) / 2;
-    constexpr int ROW = NXY + P1 + 1;   // x^a y^b, then w^k, one pad double
-    constexpr int NC = P1 * (P1 + 1) * (P1 + 2) / 6;
-    __shared__ double tab[kMpBatch * ROW];
+    constexpr int NC = n_components(P);
+    constexpr int NT = mx_cover(P).nt;
+    constexpr int ROW = 32 * NT + 2;   // per tile 16 row and 16 column monomials; pad (16-byte rows)
+    __shared__ __align__(16) double tab[B * ROW];
     const int lane = threadIdx.x;
+    const int g = lane >> 4, col = lane & 15;
 
-    // this lane's blocks: table columns of the two x^a y^b and two w^k, and the four output components
-    // (-1 where a block is partial, or where the lane has no block)
-    constexpr int NB = mp_blocks(P);
-    constexpr int BPL = (NB + 63) / 64;
-    int cx1[BPL], cx2[BPL], cz1[BPL], cz2[BPL], oc[BPL][4];
+    // The accumulator of tile t holds entry (row 4 q + g, column col) in its register q (the layout of
+    // v_mfma_f64_16x16x4f64's result); component of each, or -1
+    int oc[NT][4];
 #pragma unroll
-    for (int r = 0; r < BPL; r++) {
-        const int idx = lane + 64 * r;
-        int a1 = 0, b1 = 0, a2 = 0, b2 = -1, k1 = 0, k2 = -1;
-        if (idx < NB) mp_block(P, idx, a1, b1, a2, b2, k1, k2);
-        const bool has = idx < NB, has_x2 = b2 >= 0, has_k2 = k2 >= 0;
-        cx1[r] = xy_index(P1, a1, b1);
-        cx2[r] = has_x2 ? xy_index(P1, a2, b2) : cx1[r];
-        cz1[r] = NXY + k1;
-        cz2[r] = has_k2 ? NXY + k2 : cz1[r];
-        oc[r][0] = has ? comp_index(a1, b1, k1) : -1;
-        oc[r][1] = has && has_k2 ? comp_index(a1, b1, k2) : -1;
-        oc[r][2] = has && has_x2 ? comp_index(a2, b2, k1) : -1;
-        oc[r][3] = has && has_x2 && has_k2 ? comp_index(a2, b2, k2) : -1;
-    }
-    constexpr int NBLK_LAST = NB - 64 * (BPL - 1);   // lanes holding a block in the last round
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) oc[t][q] = kMxMap.comp[P][t][4 * q + g][col];
 
     const int64_t n_units = (a.n + kMpUnit - 1) / kMpUnit;
     const unsigned G = gridDim.x;
@@ -155,62 +258,60 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
         int prev_key = s0 > 0 ? a.keys[s0 - 1] : -1;          // cell of the slot before the unit
         const int after_key = s1 < a.n ? a.keys[s1] : -1;      // cell of the slot after it (-1: none)
         bool started_here = a.keys[s0] != prev_key;            // the current segment's cell began in this unit
-        double acc[BPL][4];
+        mx_acc acc[NT];
 #pragma unroll
-        for (int r = 0; r < BPL; r++)
-#pragma unroll
-            for (int q = 0; q < 4; q++) acc[r][q] = 0.0;
+        for (int t = 0; t < NT; t++) acc[t] = mx_acc{0.0, 0.0, 0.0, 0.0};
 
-        // the next batch's keys and coordinates are loaded while the current one is summed
-        int key_n = lane < kMpBatch && s0 + lane < s1 ? a.keys[s0 + lane] : -2;
-        float4 sp_n = lane < kMpBatch && s0 + lane < s1 ? a.spos[s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int64_t b0 = s0; b0 < s1; b0 += kMpBatch) {
-            const int nb = (int)(s1 - b0 < kMpBatch ? s1 - b0 : kMpBatch);
+        // the next batch's keys, successor keys (-3: the unit ends after the slot) and coordinates are loaded
+        // while the current one is summed
+        int key_n = lane < B && s0 + lane < s1 ? a.keys[s0 + lane] : -2;
+        int nxt_n = lane < B && s0 + lane + 1 < s1 ? a.keys[s0 + lane + 1] : -3;
+        float4 sp_n = lane < B && s0 + lane < s1 ? a.spos[s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int64_t b0 = s0; b0 < s1; b0 += B) {
+            const int nb = (int)(s1 - b0 < B ? s1 - b0 : B);
             const bool live = lane < nb;
-            const int key = key_n;
+            const int key = key_n, nxt = nxt_n;
             const float4 sp = sp_n;
-            const int64_t b1 = b0 + kMpBatch;
-            const bool live_n = lane < kMpBatch && b1 + lane < s1;
+            const int64_t b1 = b0 + B;
+            const bool live_n = lane < B && b1 + lane < s1;
             key_n = live_n ? a.keys[b1 + lane] : -2;
+            nxt_n = lane < B && b1 + lane + 1 < s1 ? a.keys[b1 + lane + 1] : -3;
             if (live_n) sp_n = a.spos[b1 + lane];
-            const int first_next = __builtin_amdgcn_readfirstlane(key_n);   // cell of slot b1 when b1 < s1
-            int nxt = __shfl_down(key, 1);
-            if (lane == nb - 1) nxt = (b1 < s1) ? first_next : ~key;         // the unit's end closes a segment
-            const uint64_t mask = __ballot(live && key != nxt);
-            if (live) {
-                const double x = sp.x, y = sp.y, z = sp.z;
-                double xp[P1], yp[P1];
-                double *row = tab + lane * ROW;
-                xp[0] = yp[0] = 1.0;
-                row[NXY] = 1.0;
-                double zk = 1.0;
+            const uint64_t mask = __ballot(live && key != nxt);   // slots that end a segment
+            if (lane < B) {
+                // this lane's particle: its row and column monomials (zeros past the batch's end)
+                const double x = live ? (double)sp.x : 0.0, y = live ? (double)sp.y : 0.0,
+                             z = live ? (double)sp.z : 0.0;
+                double xp[P1], yp[P1], zp[P1];
+                xp[0] = yp[0] = zp[0] = 1.0;
 #pragma unroll
                 for (int q = 1; q <= P; q++) {
                     xp[q] = xp[q - 1] * x;
                     yp[q] = yp[q - 1] * y;
-                    zk = zk * z;
-                    row[NXY + q] = zk;
+                    zp[q] = zp[q - 1] * z;
                 }
-#pragma unroll
-                for (int ea = 0; ea <= P; ea++)
-#pragma unroll
-                    for (int eb = 0; eb + ea <= P; eb++) row[xy_index(P1, ea, eb)] = xp[ea] * yp[eb];
+                mx_write_row<P>(tab + lane * ROW, xp, yp, zp, std::make_integer_sequence<int, 32 * NT>{});
             }
             wave_sync();
             int j = 0;
             while (j < nb) {
                 const uint64_t rest = mask >> j;
                 const int e = rest ? j + __builtin_ctzll(rest) : nb - 1;
-                for (int t = j; t <= e; t++) {
-                    const double *row = tab + t * ROW;
+                for (int t0 = j; t0 <= e; t0 += 4) {
+                    // particle t0 + g of the step; past the segment's end a row inside it is read (finite
+                    // values) and its row monomials are replaced by zeros
+                    const int r = t0 + g <= e ? t0 + g : e;
+                    const double *rp = tab + r * ROW;
+                    double av[NT], bv[NT];
 #pragma unroll
-                    for (int r = 0; r < BPL; r++) {
-                        if (r == BPL - 1 && lane >= NBLK_LAST) break;   // lanes without a block read nothing
-                        const double x1 = row[cx1[r]], x2 = row[cx2[r]], z1 = row[cz1[r]], z2 = row[cz2[r]];
-                        acc[r][0] = fma(x1, z1, acc[r][0]);
-                        acc[r][1] = fma(x1, z2, acc[r][1]);
-                        acc[r][2] = fma(x2, z1, acc[r][2]);
-                        acc[r][3] = fma(x2, z2, acc[r][3]);
+                    for (int t = 0; t < NT; t++) {
+                        av[t] = rp[32 * t + col];
+                        bv[t] = rp[32 * t + 16 + col];
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; t++) {
+                        av[t] = t0 + g <= e ? av[t] : 0.0;
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[t], 0, 0, 0);
                     }
                 }
                 if (rest) {
@@ -219,9 +320,9 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
                     const bool ends_here = (b0 + e + 1 < s1) || after_key != c;
                     if (started_here) {
                         // empty cells between the previous occupied cell and this one
-                        double *z = a.out + (int64_t)(prev_key + 1) * NC;
+                        double *zz = a.out + (int64_t)(prev_key + 1) * NC;
                         const int64_t nz = (int64_t)(c - prev_key - 1) * NC;
-                        for (int64_t i = lane; i < nz; i += 64) z[i] = 0.0;
+                        for (int64_t i = lane; i < nz; i += 64) zz[i] = 0.0;
                     }
                     double *o;
                     double scale = 1.0;
@@ -231,13 +332,19 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
                     } else {
                         o = a.partials + (2 * u + (started_here ? 1 : 0)) * NC;
                     }
+                    scale = uniform_f64(scale);   // waited for here, not at every store below
+                    double v[NT][4];
 #pragma unroll
-                    for (int r = 0; r < BPL; r++)
+                    for (int t = 0; t < NT; t++) {
 #pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            if (oc[r][q] >= 0) o[oc[r][q]] = scale * acc[r][q];
-                            acc[r][q] = 0.0;
-                        }
+                        for (int q = 0; q < 4; q++) v[t][q] = scale * acc[t][q];
+                        acc[t] = mx_acc{0.0, 0.0, 0.0, 0.0};
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; t++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++)
+                            if (oc[t][q] >= 0) o[oc[t][q]] = v[t][q];
                     prev_key = c;
                     started_here = true;
                 }
@@ -247,9 +354,9 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
         }
         if (s1 == a.n) {
             // trailing empty cells
-            double *z = a.out + (int64_t)(prev_key + 1) * NC;
+            double *zz = a.out + (int64_t)(prev_key + 1) * NC;
             const int64_t nz = (a.n_cells - 1 - prev_key) * NC;
-            for (int64_t i = lane; i < nz; i += 64) z[i] = 0.0;
+            for (int64_t i = lane; i < nz; i += 64) zz[i] = 0.0;
         }
     }
 }
@@ -257,17 +364,18 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
 // Moments of the cells that cross unit boundaries: the tail partial of the unit where the cell begins,
 // then the head partials of the units it continues into, added in a fixed order.
 template <int P>
-__global__ __launch_bounds__(64) void k_mp_combine(MpArgs a) {
-    constexpr int P1 = P + 1;
-    constexpr int NC = P1 * (P1 + 1) * (P1 + 2) / 6;
+__global__ __launch_bounds__(256) void k_mp_combine(MpArgs a) {
+    constexpr int NC = n_components(P);
     const int64_t n_units = (a.n + kMpUnit - 1) / kMpUnit;
-    for (int64_t u = 1 + blockIdx.x; u < n_units; u += gridDim.x) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // one unit boundary per wave
+    for (int64_t u = 1 + (int64_t)blockIdx.x * 4 + w; u < n_units; u += (int64_t)gridDim.x * 4) {
         const int c = a.keys[u * kMpUnit];
         if (a.keys[u * kMpUnit - 1] != c) continue;                          // no cell crosses here
         if (u >= 2 && a.keys[(u - 1) * kMpUnit - 1] == c) continue;          // crossed an earlier boundary
         const int64_t last = (a.cs[c + 1] - 1) / kMpUnit;                     // unit of the cell's last slot
         const double m = a.n_boxes > 1 ? a.mass[box_of_cell(a.boxes, a.n_boxes, c)] : a.mass[0];
-        for (int i = threadIdx.x; i < NC; i += 64) {
+        for (int i = lane; i < NC; i += 64) {
             // head partials of units u..last in four interleaved running sums (loads in flight), added in
             // a fixed order
             double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
@@ -288,22 +396,22 @@ __global__ __launch_bounds__(64) void k_mp_combine(MpArgs a) {
 typedef void (*MpKernel)(MpArgs);
 
 template <int P>
-void pick_mp(int p, bool narrow, MpKernel &main, MpKernel &combine) {
+void pick_mp(int p, MpKernel &main, MpKernel &combine) {
     if constexpr (P > kMaxOrder) {
         main = combine = nullptr;
     } else {
         if (p == P) {
-            main = narrow ? k_multipoles<P, kMpBatchNarrow> : k_multipoles<P, kMpBatchWide>;
+            main = k_multipoles<P, kMxBatch>;
             combine = k_mp_combine<P>;
         } else {
-            pick_mp<P + 1>(p, narrow, main, combine);
+            pick_mp<P + 1>(p, main, combine);
         }
     }
 }
 
 }  // namespace
 
-int multipole_components(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+int multipole_components(int p) { return n_components(p); }
 
 int multipole_max_order() { return kMaxOrder; }
 
@@ -317,7 +425,7 @@ hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const int3
                              int64_t n_cells, int p, const double *mass_host, double *mass_dev, double *partials,
                              double *out, int device, hipStream_t st) {
     MpKernel kmain = nullptr, kcomb = nullptr;
-    pick_mp<0>(p, n < 16 * n_cells, kmain, kcomb);
+    pick_mp<0>(p, kmain, kcomb);
     if (!kmain) return hipErrorInvalidValue;
     for (int first = 0; first < n_boxes; first += kMpChunk) {
         MassChunk ch;
@@ -356,8 +464,8 @@ hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const int3
     hipLaunchKernelGGL(kmain, dim3((unsigned)grid), dim3(64), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_units < 2) return e;
-    const int64_t cgrid = std::min<int64_t>(n_units - 1, (int64_t)cus * 8);
-    hipLaunchKernelGGL(kcomb, dim3((unsigned)cgrid), dim3(64), 0, st, a);
+    const int64_t cgrid = std::min<int64_t>((n_units - 1 + 3) / 4, (int64_t)1 << 20);   // a boundary per wave
+    hipLaunchKernelGGL(kcomb, dim3((unsigned)cgrid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
