@@ -198,23 +198,32 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_hist(const int32_t *__re
 // round, lanes with equal digits are found with one ballot per digit bit; a
 // lane's rank is the number of equal lanes below it plus the wave's running
 // count of that digit.  Wave counts are then prefix-summed across the four
-// waves, and the tile's global offset per digit comes from the scanned
-// (digit, tile) histogram.  Order within a digit is the input order.
+// waves, and the tile's digit totals across the digits: every element gets
+// its position in the tile sorted by digit (input order within a digit).  The
+// tile is staged in LDS in that order and written out by consecutive threads,
+// so each digit's run goes to global memory in whole, contiguous pieces at
+// the tile's global offset for the digit (from the scanned (digit, tile)
+// histogram).
 __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(const int32_t *__restrict__ kin,
                                                                 const int32_t *__restrict__ vin,
                                                                 int32_t *__restrict__ kout,
                                                                 int32_t *__restrict__ vout, int64_t n, int shift,
                                                                 int bits, const uint32_t *__restrict__ toff,
                                                                 int ntiles) {
+    static_assert(kTileThreads == kRadixBins, "one thread per digit in the per-digit steps");
     __shared__ uint32_t wcnt[4][kRadixBins];
     __shared__ uint32_t goff[kRadixBins];
+    __shared__ uint32_t loff[kRadixBins];
+    __shared__ int32_t skey[kTile];
+    __shared__ int32_t sval[kTile];
     int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     for (int d = tid; d < 4 * kRadixBins; d += kTileThreads) (&wcnt[0][0])[d] = 0;
     if (tid < (1 << bits)) goff[tid] = toff[(int64_t)tid * ntiles + blockIdx.x];
     __syncthreads();
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t below_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * kWaveSpan;
+    const int64_t tile = (int64_t)blockIdx.x * kTile;
+    const int64_t base = tile + (int64_t)w * kWaveSpan;
     int32_t key[kTileItems], val[kTileItems];
     uint32_t rank[kTileItems];
 #pragma unroll
@@ -237,23 +246,58 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(const int32_t *_
         if (valid && below == 0) wcnt[w][d] = c0 + cnt;
     }
     __syncthreads();
-    if (tid < kRadixBins) {
+    {
+        // digit tid: prefix over the waves, and the tile's total
         uint32_t run = 0;
         for (int w2 = 0; w2 < 4; w2++) {
             uint32_t c = wcnt[w2][tid];
             wcnt[w2][tid] = run;
             run += c;
         }
+        loff[tid] = run;
+    }
+    __syncthreads();
+    if (w == 0) {
+        // exclusive scan of the tile's digit totals: four digits per lane, then a wave scan of the lane sums
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            v[q] = s;
+            s += loff[4 * lane + q];
+        }
+        uint32_t incl = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        const uint32_t excl = incl - s;
+#pragma unroll
+        for (int q = 0; q < 4; q++) loff[4 * lane + q] = excl + v[q];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kTileItems; r++) {
         int64_t i = base + (int64_t)r * 64 + lane;
         if (i < n) {
-            uint32_t d = ((uint32_t)key[r] >> shift) & mask;
-            uint32_t dest = goff[d] + wcnt[w][d] + rank[r];
-            kout[dest] = key[r];
-            vout[dest] = val[r];
+            const uint32_t d = ((uint32_t)key[r] >> shift) & mask;
+            const uint32_t lp = loff[d] + wcnt[w][d] + rank[r];
+            skey[lp] = key[r];
+            sval[lp] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t left = n - tile;
+    const int tile_n = left < kTile ? (int)left : kTile;
+#pragma unroll 4
+    for (int j = 0; j < kTileItems; j++) {
+        const int lp = j * kTileThreads + tid;
+        if (lp < tile_n) {
+            const int32_t k = skey[lp];
+            const uint32_t d = ((uint32_t)k >> shift) & mask;
+            const uint32_t dest = goff[d] + ((uint32_t)lp - loff[d]);
+            kout[dest] = k;
+            vout[dest] = sval[lp];
         }
     }
 }
