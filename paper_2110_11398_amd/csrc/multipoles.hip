@@ -231,9 +231,12 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
     constexpr int NC = n_components(P);
     constexpr int NT = mx_cover(P).nt;
     constexpr int ROW = 32 * NT + 2;   // per tile 16 row and 16 column monomials; pad (16-byte rows)
-    __shared__ __align__(16) double tab[B * ROW];
+    // B rows written every batch (finite values: lanes past the batch's end write the monomials of 0), then 3
+    // zero rows, so that a step may read rows up to 3 past a segment's end without a bound
+    __shared__ __align__(16) double tab[(B + 3) * ROW];
     const int lane = threadIdx.x;
     const int g = lane >> 4, col = lane & 15;
+    for (int i = lane; i < 3 * ROW; i += 64) tab[B * ROW + i] = 0.0;
 
     // The accumulator of tile t holds entry (row 4 q + g, column col) in its register q (the layout of
     // v_mfma_f64_16x16x4f64's result); component of each, or -1
@@ -297,11 +300,9 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
             while (j < nb) {
                 const uint64_t rest = mask >> j;
                 const int e = rest ? j + __builtin_ctzll(rest) : nb - 1;
-                for (int t0 = j; t0 <= e; t0 += 4) {
-                    // particle t0 + g of the step; past the segment's end a row inside it is read (finite
-                    // values) and its row monomials are replaced by zeros
-                    const int r = t0 + g <= e ? t0 + g : e;
-                    const double *rp = tab + r * ROW;
+                const double *rp = tab + (j + g) * ROW;
+                for (int t0 = j; t0 <= e; t0 += 4, rp += 4 * ROW) {
+                    // particle t0 + g of the step; past the segment's end its row monomials are replaced by zeros
                     double av[NT], bv[NT];
 #pragma unroll
                     for (int t = 0; t < NT; t++) {
