@@ -37,7 +37,7 @@ namespace anf {
 namespace {
 
 constexpr int kMaxOrder = 10;
-constexpr int kMpUnit = 1024;   // slots per work unit
+constexpr int kMpUnit = 1536;   // slots per work unit (measured: 1024, 2048 slower by 1.5 and 1%)
 constexpr int kMxBatch = 32;   // slots per batch (rows of the LDS monomial table)
 
 __device__ inline void wave_sync() {

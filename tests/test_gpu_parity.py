@@ -828,9 +828,9 @@ def test_multipoles_sparse_cells(nf):
     c.free()
 
 
-@pytest.mark.parametrize("n_in_cell", [2047, 2048, 2049, 4096, 6001])
+@pytest.mark.parametrize("n_in_cell", [1535, 1536, 1537, 3072, 3073, 6001, 9217])
 def test_multipoles_unit_boundaries_and_determinism(nf, n_in_cell):
-    """The sorted particles are cut into units of 1024 slots, so a heavy cell spans two to seven units whose
+    """The sorted particles are cut into units of 1536 slots, so a heavy cell spans two to eight units whose
     partials are combined; two calls give bit-identical moments."""
     K = 8
     p = _mp_cell_of(n_in_cell, K)
