@@ -846,6 +846,20 @@ def test_multipoles_unit_boundaries_and_determinism(nf, n_in_cell):
     c.free()
 
 
+def test_multipoles_clustered_full_size(nf, clustered_full):
+    """Every cell of the clustered workload (N=256^3, K=64: 262144 cells; the heaviest holds ~10^5 particles and
+    spans some seventy work units) against the oracle's order-8 moments."""
+    b = clustered_full
+    c = nf.build_cells(torch.from_numpy(b.pos).cuda(), [(b.n, b.box, b.K)], 2)
+    got = c.multipoles(8, [b.gm]).cpu().numpy()
+    nf.sync()
+    ref = oracle.multipoles(b.pos, b.box, b.K, 8, b.gm)
+    counts = np.bincount(oracle.bin_cells(b.pos, b.box, b.K), minlength=b.K ** 3)
+    assert counts.max() > 40 * 1536
+    _mp_check(got, ref, counts, b.gm, "multipoles clustered full")
+    c.free()
+
+
 # ---------------------------------------------------------------- far field from cell Taylor series (Sec. 3.1)
 
 def _ty_exponent_degrees(p):
