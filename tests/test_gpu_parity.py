@@ -92,12 +92,15 @@ def expected_cells(pos, boxes):
     return perm.astype(np.int32), start, rel[perm], keys[perm].astype(np.int32)
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged", "faces", "multibox", "one_cell", "sparse", "wrapped"])
+@pytest.mark.parametrize("case", ["tiny", "ragged", "faces", "multibox", "one_cell", "sparse", "wrapped", "clustered"])
 def test_build_cells_is_exact(nf, case):
     rng = np.random.default_rng(zlib.crc32(case.encode()))
     if case == "tiny":
         w = gen.workload("tiny")
         pos, boxes = w.boxes[0].pos, [(w.boxes[0].n, 1.0, 8)]
+    elif case == "clustered":   # the full clustered workload: 16.7M particles, 18-bit keys, three radix passes
+        b = gen.workload("clustered").boxes[0]
+        pos, boxes = b.pos, [(b.n, b.box, b.K)]
     elif case == "ragged":
         pos = rng.random((1_000_003, 3)).astype(np.float32)
         boxes = [(len(pos), 1.0, 37)]
