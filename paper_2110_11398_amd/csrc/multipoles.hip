@@ -363,34 +363,43 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
 }
 
 // Moments of the cells that cross unit boundaries: the tail partial of the unit where the cell begins,
-// then the head partials of the units it continues into, added in a fixed order.
+// then the head partials of the units it continues into, added in a fixed order.  One workgroup per boundary:
+// wave w sums the head partials of units u + w, u + w + 4, ... in four interleaved running sums (a halo core
+// spans tens of units, so sixteen partials' loads are in flight at a time), and the first wave adds the four
+// waves' sums in a fixed order.
 template <int P>
 __global__ __launch_bounds__(256) void k_mp_combine(MpArgs a) {
     constexpr int NC = n_components(P);
+    __shared__ double part[4][NC];
     const int64_t n_units = (a.n + kMpUnit - 1) / kMpUnit;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // one unit boundary per wave
-    for (int64_t u = 1 + (int64_t)blockIdx.x * 4 + w; u < n_units; u += (int64_t)gridDim.x * 4) {
+    for (int64_t u = 1 + blockIdx.x; u < n_units; u += gridDim.x) {
+        // the same u for the whole workgroup: the tests below are uniform
         const int c = a.keys[u * kMpUnit];
         if (a.keys[u * kMpUnit - 1] != c) continue;                          // no cell crosses here
         if (u >= 2 && a.keys[(u - 1) * kMpUnit - 1] == c) continue;          // crossed an earlier boundary
         const int64_t last = (a.cs[c + 1] - 1) / kMpUnit;                     // unit of the cell's last slot
-        const double m = a.n_boxes > 1 ? a.mass[box_of_cell(a.boxes, a.n_boxes, c)] : a.mass[0];
         for (int i = lane; i < NC; i += 64) {
-            // head partials of units u..last in four interleaved running sums (loads in flight), added in
-            // a fixed order
             double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-            int64_t v = u;
-            for (; v + 3 <= last; v += 4) {
+            int64_t v = u + w;
+            for (; v + 12 <= last; v += 16) {
                 t0 += a.partials[(2 * v) * NC + i];
-                t1 += a.partials[(2 * v + 2) * NC + i];
-                t2 += a.partials[(2 * v + 4) * NC + i];
-                t3 += a.partials[(2 * v + 6) * NC + i];
+                t1 += a.partials[(2 * v + 8) * NC + i];
+                t2 += a.partials[(2 * v + 16) * NC + i];
+                t3 += a.partials[(2 * v + 24) * NC + i];
             }
-            for (; v <= last; v++) t0 += a.partials[(2 * v) * NC + i];
-            const double t = a.partials[(2 * (u - 1) + 1) * NC + i] + ((t0 + t1) + (t2 + t3));
-            a.out[(int64_t)c * NC + i] = m * t;
+            for (; v <= last; v += 4) t0 += a.partials[(2 * v) * NC + i];
+            part[w][i] = (t0 + t1) + (t2 + t3);
         }
+        __syncthreads();
+        if (w == 0) {
+            const double m = a.n_boxes > 1 ? a.mass[box_of_cell(a.boxes, a.n_boxes, c)] : a.mass[0];
+            for (int i = lane; i < NC; i += 64) {
+                const double heads = (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
+                a.out[(int64_t)c * NC + i] = m * (a.partials[(2 * (u - 1) + 1) * NC + i] + heads);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -465,7 +474,7 @@ hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const int3
     hipLaunchKernelGGL(kmain, dim3((unsigned)grid), dim3(64), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_units < 2) return e;
-    const int64_t cgrid = std::min<int64_t>((n_units - 1 + 3) / 4, (int64_t)1 << 20);   // a boundary per wave
+    const int64_t cgrid = std::min<int64_t>(n_units - 1, (int64_t)1 << 20);   // a boundary per workgroup
     hipLaunchKernelGGL(kcomb, dim3((unsigned)cgrid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
