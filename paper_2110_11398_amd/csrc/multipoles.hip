@@ -225,7 +225,10 @@ __global__ void k_zero_f64(double *p, int64_t n) {
         p[i] = 0.0;
 }
 
-template <int P, int B>
+// STAGE: each cell's components go through LDS into component order and are written by consecutive lanes
+// (whole cache lines; pays where cells are small and the per-cell output dominates), else each lane stores its
+// accumulator entries directly (no LDS for it: one more wave per CU).
+template <int P, int B, bool STAGE>
 __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
     constexpr int P1 = P + 1;
     constexpr int NC = n_components(P);
@@ -234,6 +237,7 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
     // B rows written every batch (finite values: lanes past the batch's end write the monomials of 0), then 3
     // zero rows, so that a step may read rows up to 3 past a segment's end without a bound
     __shared__ __align__(16) double tab[(B + 3) * ROW];
+    __shared__ double out_stage[STAGE ? NC : 1];   // one cell's components in component order
     const int lane = threadIdx.x;
     const int g = lane >> 4, col = lane & 15;
     for (int i = lane; i < 3 * ROW; i += 64) tab[B * ROW + i] = 0.0;
@@ -334,18 +338,31 @@ __global__ __launch_bounds__(64) void k_multipoles(MpArgs a) {
                         o = a.partials + (2 * u + (started_here ? 1 : 0)) * NC;
                     }
                     scale = uniform_f64(scale);   // waited for here, not at every store below
-                    double v[NT][4];
+                    if constexpr (STAGE) {
 #pragma unroll
-                    for (int t = 0; t < NT; t++) {
+                        for (int t = 0; t < NT; t++) {
 #pragma unroll
-                        for (int q = 0; q < 4; q++) v[t][q] = scale * acc[t][q];
-                        acc[t] = mx_acc{0.0, 0.0, 0.0, 0.0};
+                            for (int q = 0; q < 4; q++)
+                                if (oc[t][q] >= 0) out_stage[oc[t][q]] = scale * acc[t][q];
+                            acc[t] = mx_acc{0.0, 0.0, 0.0, 0.0};
+                        }
+                        wave_sync();
+                        for (int i = lane; i < NC; i += 64) o[i] = out_stage[i];
+                        wave_sync();
+                    } else {
+                        double v[NT][4];
+#pragma unroll
+                        for (int t = 0; t < NT; t++) {
+#pragma unroll
+                            for (int q = 0; q < 4; q++) v[t][q] = scale * acc[t][q];
+                            acc[t] = mx_acc{0.0, 0.0, 0.0, 0.0};
+                        }
+#pragma unroll
+                        for (int t = 0; t < NT; t++)
+#pragma unroll
+                            for (int q = 0; q < 4; q++)
+                                if (oc[t][q] >= 0) o[oc[t][q]] = v[t][q];
                     }
-#pragma unroll
-                    for (int t = 0; t < NT; t++)
-#pragma unroll
-                        for (int q = 0; q < 4; q++)
-                            if (oc[t][q] >= 0) o[oc[t][q]] = v[t][q];
                     prev_key = c;
                     started_here = true;
                 }
@@ -406,15 +423,15 @@ __global__ __launch_bounds__(256) void k_mp_combine(MpArgs a) {
 typedef void (*MpKernel)(MpArgs);
 
 template <int P>
-void pick_mp(int p, MpKernel &main, MpKernel &combine) {
+void pick_mp(int p, bool stage, MpKernel &main, MpKernel &combine) {
     if constexpr (P > kMaxOrder) {
         main = combine = nullptr;
     } else {
         if (p == P) {
-            main = k_multipoles<P, kMxBatch>;
+            main = stage ? k_multipoles<P, kMxBatch, true> : k_multipoles<P, kMxBatch, false>;
             combine = k_mp_combine<P>;
         } else {
-            pick_mp<P + 1>(p, main, combine);
+            pick_mp<P + 1>(p, stage, main, combine);
         }
     }
 }
@@ -435,7 +452,9 @@ hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const int3
                              int64_t n_cells, int p, const double *mass_host, double *mass_dev, double *partials,
                              double *out, int device, hipStream_t st) {
     MpKernel kmain = nullptr, kcomb = nullptr;
-    pick_mp<0>(p, kmain, kcomb);
+    // cells of fewer than 16 particles on average: the per-cell output dominates, stage it (measured on the
+    // late-time workload, 8 per cell: 9.33 -> 8.47 ms; on the clustered one, 64 per cell, staging costs 5%)
+    pick_mp<0>(p, n < 16 * n_cells, kmain, kcomb);
     if (!kmain) return hipErrorInvalidValue;
     for (int first = 0; first < n_boxes; first += kMpChunk) {
         MassChunk ch;
