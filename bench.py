@@ -588,7 +588,7 @@ def run_multipoles(args, nf, torch, w, pos, boxes):
             "config": {"workload": f"{args.workload}: {w.description}", "n": n, "cells": nc, "order": p,
                        "components": ncomp},
             "roofline": _roofline(nbytes, flops, ms,
-                                  "abacus_nf_multipoles call (k_mp_units, scans, k_multipoles, k_mp_combine)")}
+                                  "abacus_nf_multipoles call (k_set_mass, k_multipoles, k_mp_combine)")}
 
 
 if __name__ == "__main__":
