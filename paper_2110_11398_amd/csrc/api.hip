@@ -504,8 +504,8 @@ int abacus_nf_taylor_forces(abacus_nf_cells h, int32_t order, const double *tayl
     if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorUnknown);
     if (dev != h->device) return ABACUS_NF_ESTATE;
     if (h->n_total == 0) return ABACUS_NF_OK;
-    hipError_t e = launch_taylor(h->spos, h->keys, h->perm, h->d_boxes, h->n_boxes, h->n_total, order, taylor,
-                                 acc, dev, (hipStream_t)hip_stream);
+    hipError_t e = launch_taylor(h->spos, h->keys, h->perm, h->d_boxes, h->n_boxes, h->n_total, h->n_cells, order,
+                                 taylor, acc, dev, (hipStream_t)hip_stream);
     return e == hipSuccess ? ABACUS_NF_OK : hip_fail(e);
 }
 

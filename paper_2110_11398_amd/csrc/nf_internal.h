@@ -199,8 +199,8 @@ hipError_t launch_multipoles(const float4 *spos, const int32_t *keys, const int3
 // Far field from cell Taylor series (taylor.hip)
 int taylor_max_order();
 hipError_t launch_taylor(const float4 *spos, const int32_t *keys, const int32_t *perm, const BoxDev *boxes,
-                         int n_boxes, int64_t n, int p, const double *taylor, float *acc, int device,
-                         hipStream_t st);
+                         int n_boxes, int64_t n, int64_t n_cells, int p, const double *taylor, float *acc,
+                         int device, hipStream_t st);
 
 // Work list and forces (forces.hip)
 struct ForcesArgs {

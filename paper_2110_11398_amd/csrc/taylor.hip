@@ -29,7 +29,10 @@ namespace anf {
 namespace {
 
 constexpr int kTyMaxOrder = 10;
-constexpr int kTyStageBytes = 8192;   // LDS per wave for staged coefficients (20 waves per CU)
+// LDS per wave for staged coefficients: 8 KB (20 waves per CU), or 16 KB where cells hold fewer than 16
+// particles on average, so that a step of 64 slots spans twice as many cells (measured, order 8: late-time
+// workload 10.24 -> 8.39 ms; the clustered workload, 64 per cell, 0.61 -> 0.77 ms with the larger stage)
+constexpr int kTyStageBytes = 8192, kTyStageBytesSparse = 16384;
 
 // Position of component (a, b, k) in the degree / a-descending / b-descending order.
 __host__ __device__ constexpr int comp_index(int a, int b, int k) {
@@ -89,10 +92,10 @@ __device__ __forceinline__ void taylor_gradient(const double *__restrict__ T, do
     }
 }
 
-template <int P>
+template <int P, int STAGE_BYTES>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 9 ? 2 : 4, 8))) void k_taylor(TyArgs a, const double *__restrict__ taylor) {
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
-    constexpr int kCells = kTyStageBytes / (NC * 8) > 0 ? kTyStageBytes / (NC * 8) : 1;
+    constexpr int kCells = STAGE_BYTES / (NC * 8) > 0 ? STAGE_BYTES / (NC * 8) : 1;
     __shared__ double tc[kCells * NC];
     const int lane = threadIdx.x;
     // XCD-aware contiguous chunks of slots: block i runs on XCD i % 8; the blocks of one XCD take adjacent chunks
@@ -187,11 +190,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 9 ? 2 :
 typedef void (*TyKernel)(TyArgs, const double *);
 
 template <int P>
-TyKernel pick_taylor(int p) {
+TyKernel pick_taylor(int p, bool sparse) {
     if constexpr (P > kTyMaxOrder) {
         return nullptr;
     } else {
-        return p == P ? k_taylor<P> : pick_taylor<P + 1>(p);
+        if (p == P) return sparse ? k_taylor<P, kTyStageBytesSparse> : k_taylor<P, kTyStageBytes>;
+        return pick_taylor<P + 1>(p, sparse);
     }
 }
 
@@ -200,10 +204,10 @@ TyKernel pick_taylor(int p) {
 int taylor_max_order() { return kTyMaxOrder; }
 
 hipError_t launch_taylor(const float4 *spos, const int32_t *keys, const int32_t *perm, const BoxDev *boxes,
-                         int n_boxes, int64_t n, int p, const double *taylor, float *acc, int device,
-                         hipStream_t st) {
+                         int n_boxes, int64_t n, int64_t n_cells, int p, const double *taylor, float *acc,
+                         int device, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    TyKernel kfn = pick_taylor<0>(p);
+    TyKernel kfn = pick_taylor<0>(p, n < 16 * n_cells);
     if (!kfn) return hipErrorInvalidValue;
     TyArgs a;
     a.spos = spos;

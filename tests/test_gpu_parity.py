@@ -934,6 +934,24 @@ def test_taylor_co_added_to_near_field(nf, tiny, kind):
     c.free()
 
 
+@pytest.mark.parametrize("order", [4, 8, 10])
+def test_taylor_sparse_cells(nf, order):
+    """About three particles per cell (and empty cells): the form that stages twice as many cells' coefficients
+    per step of 64 slots."""
+    rng = np.random.default_rng(40 + order)
+    K = 24
+    p = rng.random((40000, 3)).astype(np.float32)
+    T = gen.taylor_coefficients(K ** 3, order, seed=50 + order)
+    c = nf.build_cells(torch.from_numpy(p).cuda(), [(len(p), 1.0, K)], 2)
+    acc = torch.zeros((len(p), 3), dtype=torch.float32, device="cuda")
+    c.taylor_forces(order, torch.from_numpy(T).cuda(), acc)
+    got = acc.cpu().numpy().astype(np.float64)
+    nf.sync()
+    ref = oracle.taylor_forces(p, 1.0, K, order, T)
+    _ty_check(got, ref, p, 1.0, K, order, T, f"taylor sparse order={order}")
+    c.free()
+
+
 def test_taylor_batched_boxes_and_heavy_cells(nf):
     w = gen.workload("batched", n_boxes=5, lo=20 ** 3, hi=40 ** 3)
     pos = torch.from_numpy(w.concat_positions()).cuda()
