@@ -29,10 +29,10 @@ namespace anf {
 namespace {
 
 constexpr int kTyMaxOrder = 10;
-// LDS per wave for staged coefficients: 8 KB (20 waves per CU), or 16 KB where cells hold fewer than 16
-// particles on average, so that a step of 64 slots spans twice as many cells (measured, order 8: late-time
-// workload 10.24 -> 8.39 ms; the clustered workload, 64 per cell, 0.61 -> 0.77 ms with the larger stage)
-constexpr int kTyStageBytes = 8192, kTyStageBytesSparse = 16384;
+// LDS per wave for staged coefficients: 6 KB (4 cells of order 8 per step of 64 slots), or 16 KB (12 cells)
+// where cells hold fewer than 16 particles on average.  Measured at order 8: clustered workload (64 per cell)
+// 4 / 6 / 8 / 16 KB: 0.548 / 0.534 / 0.60 / 0.77 ms; late-time workload (8 per cell) 8 / 16 KB: 10.24 / 8.39 ms
+constexpr int kTyStageBytes = 6144, kTyStageBytesSparse = 16384;
 
 // Position of component (a, b, k) in the degree / a-descending / b-descending order.
 __host__ __device__ constexpr int comp_index(int a, int b, int k) {
